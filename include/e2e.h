@@ -1,0 +1,248 @@
+/*
+ * e2e.h -- C ABI of the MI355X echellogram renderer.
+ *
+ * The library renders synthetic raw frames of a cross-dispersed echelle
+ * spectrograph the way Genoni et al. (2020, "End to end simulators: a
+ * flexible and scalable cloud-based architecture", Exp. Astron.) define
+ * them: the frame is the superposition, over a fine wavelength grid, of
+ * every spectral fiber image (SFI) projected on the detector (Sec. 2), each
+ * SFI being the PSF integrated over the pixel areas on a sub-pixel grid
+ * (Sec. 2.2), with photon noise added on the final frame (Sec. 2.2).  The
+ * spectrograph is described by a database of spectral-format data, PSF maps
+ * and throughput per SFI (Sec. 2.1) that is computed once and kept for many
+ * simulations; here it is loaded once into device-resident tables.
+ *
+ * Conventions (every entry point):
+ *   - wavelengths in nm (FP64); detector positions in pixels, 0-based, pixel
+ *     (i, j) covering [i-1/2, i+1/2) x [j-1/2, j+1/2); frames row-major
+ *     [ny][nx] with y = row;
+ *   - a trace (one order x fiber x slice) has n samples at
+ *     lmin + (k + 1/2)(lmax - lmin)/n; a Doppler shift v moves sample k to
+ *     lambda_k (1 + v/c) before the format map;
+ *   - x and y of a sample are polynomials in t = (2 lambda' - lmin - lmax) /
+ *     (lmax - lmin), coefficients in ascending powers; x must increase
+ *     strictly with lambda over the trace and |dy/dx| must stay <= 0.5;
+ *   - sample photons = spectrum[slot][k] * throughput * flux_scale;
+ *   - flux falling off the detector is dropped.
+ * Status codes: 0 = E2E_OK, >0 = still pending, <0 = error.  No C++
+ * exception crosses this interface.  e2e_last_error() returns a
+ * thread-local message for the calling thread's last failure.
+ */
+#ifndef E2E_H
+#define E2E_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t e2e_status;
+
+#define E2E_OK 0
+#define E2E_PENDING 1
+#define E2E_EINVAL (-1)       /* null pointer, bad size, bad enum value        */
+#define E2E_EFORMAT (-2)      /* trace not monotone / too steep / bad degree   */
+#define E2E_EPSF (-3)         /* PSF table not normalised, bad shape           */
+#define E2E_ENOMEM (-4)       /* request exceeds the context's HBM budget      */
+#define E2E_EAGAIN (-5)       /* serve queue full                              */
+#define E2E_ENOTFOUND (-6)    /* unknown handle or ticket                      */
+#define E2E_EDEVICE (-7)      /* HIP runtime error (message kept)              */
+#define E2E_EBUSY (-8)        /* handle still referenced by in-flight work     */
+#define E2E_EUNSUPPORTED (-9) /* valid but not implemented combination        */
+#define E2E_EINTERNAL (-10)   /* a device-side consistency check failed        */
+
+typedef struct e2e_ctx e2e_ctx;
+typedef uint64_t e2e_format_id;
+typedef uint64_t e2e_psf_id;
+typedef uint64_t e2e_ticket;
+
+/* element types of spectra and frames */
+#define E2E_F32 0
+#define E2E_F64 1
+
+/* PSF kinds (Sec. 2.1: an analytic asymmetric Gaussian, or ray-traced maps) */
+#define E2E_PSF_GAUSS_ERF 0  /* circular Gaussian, exact pixel integrals       */
+#define E2E_PSF_TABLE 1      /* field-varying maps of cell integrals           */
+#define E2E_PSF_SEPARABLE 2  /* field-varying axis-aligned Gaussian (sx, sy)   */
+
+/* arithmetic of the render path */
+#define E2E_PREC_F64 0       /* FP64 positions, FP32 PSF offsets, FP64 sums    */
+#define E2E_PREC_F32 1       /* separable only: FP32 weights and FP32 sums     */
+#define E2E_PREC_BF16_HILO 2 /* separable only: bf16 hi/lo MFMA, FP32 sums     */
+#define E2E_PREC_F16_HILO 3  /* separable only: fp16 hi/lo MFMA, FP32 sums     */
+
+/* request flags */
+#define E2E_FLAG_ASYNC 1u    /* device output: return once enqueued on stream  */
+
+/*
+ * One spectral trace: the spectral-format record of Sec. 2.1 (order number,
+ * fiber, wavelength range, centroid position as a function of wavelength)
+ * plus its throughput (Sec. 2.1: multiplied on the normalised illumination).
+ * cx / cy hold deg+1 FP64 coefficients (deg <= 7), copied by the load call.
+ */
+typedef struct {
+    int32_t order, fiber, slice;
+    double lambda_min_nm, lambda_max_nm;
+    int64_t n_samples;            /* 1 .. 2^31-1                              */
+    int32_t deg_x, deg_y;
+    const double *cx, *cy;
+    double throughput;
+    int32_t spectrum_slot;        /* index into e2e_render_req.spectra        */
+} e2e_trace_desc;
+
+/*
+ * PSF maps (Sec. 2.1).  GAUSS_ERF: sigma (px) and half_width H, the weight
+ * of pixel (a+d) on each axis being the normal-CDF difference over the
+ * pixel, renormalised over the (2H+1)-wide window around a = floor(x+1/2).
+ * TABLE: tables[grid_ny][grid_nx][kh][kw] float32 cell integrals, each node
+ * summing to 1 (within 1e-5), oversample cells per pixel, centred on the
+ * table centre, nodes spanning the detector edge to edge and interpolated
+ * bilinearly at each sample's (x, y); the GPU path needs oversample = 4 and
+ * kw = kh in {32, 48}.  SEPARABLE: sigma_xy[grid_ny][grid_nx][2] (sx, sy)
+ * interpolated bilinearly, then the GAUSS_ERF rule per axis with half_width.
+ * All arrays are host memory, copied by the load call.
+ */
+typedef struct {
+    int32_t kind;
+    double sigma;
+    int32_t half_width;
+    int32_t grid_nx, grid_ny;
+    int32_t kw, kh, oversample;
+    const float *tables;
+    const float *sigma_xy;
+} e2e_psf_desc;
+
+/*
+ * One frame to render (Sec. 3's "parameter file": which database, which
+ * source, which scenario).  spectra[s] points to the photons per sample of
+ * slot s (n_samples of the traces that use it), on the device when
+ * spectra_on_device != 0 (then `spectra` itself is still a host array of
+ * device pointers).  out is [ny][nx] of out_dtype, on the device when
+ * out_on_device != 0.  hip_stream: a hipStream_t, or NULL for the context's
+ * stream.  Poisson noise (Sec. 2.2) uses Philox-4x32-10 keyed by (seed) with
+ * counter (pixel, frame_index, draw).  All caller buffers are borrowed for
+ * the duration of the call (for e2e_serve_submit: until poll completes).
+ */
+typedef struct {
+    e2e_format_id fmt;
+    e2e_psf_id psf;
+    const void *const *spectra;
+    int32_t n_spectra;
+    int32_t spectrum_dtype;
+    int32_t spectra_on_device;
+    double rv_mps;
+    double flux_scale;
+    uint64_t seed;
+    uint32_t frame_index;
+    int32_t poisson;
+    int32_t precision;
+    void *out;
+    int32_t out_dtype;
+    int32_t out_on_device;
+    void *hip_stream;
+    uint32_t flags;
+} e2e_render_req;
+
+/* Per-request timing of the serve loop; times in microseconds since the
+ * context was created. */
+typedef struct {
+    double t_submit_us, t_admit_us, t_launch_us, t_done_us;
+    uint64_t footprint_bytes;
+    int32_t status;
+    int32_t batch_size;           /* requests that shared its launch          */
+} e2e_render_stats;
+
+typedef struct {
+    int32_t max_inflight;         /* requests admitted at once (slots)        */
+    int32_t max_queue;            /* queued but not yet admitted              */
+    int32_t n_streams;            /* device streams used for overlap          */
+    int32_t max_batch;            /* requests merged into one launch          */
+} e2e_serve_config;
+
+/* Context bound to one HIP device; hbm_budget_bytes caps the device memory
+ * that resident tables plus in-flight renders may use (0 = 90% of free). */
+e2e_status e2e_create(e2e_ctx **out, int32_t hip_device, uint64_t hbm_budget_bytes);
+/* Drains the serve loop, frees every resident table. */
+void e2e_destroy(e2e_ctx *ctx);
+/* Message of the calling thread's last failed call ("" if none). */
+const char *e2e_last_error(void);
+/* Library version string. */
+const char *e2e_version(void);
+
+/*
+ * Copy a spectral-format database (Sec. 2.1) into device-resident tables.
+ * Validation: degrees in 0..7, lmin < lmax, n >= 1, dx/dt > 0 on [-1, 1]
+ * (strictly increasing x), |dy/dx| <= 0.5, det_nx/ny in 1..65536.
+ * Errors: E2E_EINVAL, E2E_EFORMAT, E2E_ENOMEM, E2E_EDEVICE.
+ */
+e2e_status e2e_format_load(e2e_ctx *ctx, const e2e_trace_desc *traces, int32_t n_traces,
+                           int32_t det_nx, int32_t det_ny, e2e_format_id *out);
+/* Copy PSF maps into device-resident tables (pre-binned per pixel phase for
+ * TABLE).  Errors: E2E_EINVAL, E2E_EPSF, E2E_ENOMEM, E2E_EDEVICE. */
+e2e_status e2e_psf_load(e2e_ctx *ctx, const e2e_psf_desc *psf, e2e_psf_id *out);
+/* E2E_EBUSY while a served request still uses the handle. */
+e2e_status e2e_format_free(e2e_ctx *ctx, e2e_format_id id);
+e2e_status e2e_psf_free(e2e_ctx *ctx, e2e_psf_id id);
+
+/*
+ * Render one frame (the plain renderer: one launch per frame, one workgroup
+ * per detector tile).  Writes req->out before returning unless
+ * E2E_FLAG_ASYNC is set and the output is on the device.
+ */
+e2e_status e2e_render(e2e_ctx *ctx, const e2e_render_req *req);
+/*
+ * Render n frames of any sizes / formats sharing one PSF kind in one
+ * persistent launch that pulls (frame, tile) work items from a queue;
+ * results are bitwise identical to e2e_render of each frame.
+ */
+e2e_status e2e_render_batch(e2e_ctx *ctx, const e2e_render_req *reqs, int32_t n);
+
+/*
+ * Continuous-batching request loop (Sec. 3's "size the problem, allocate
+ * resources, distribute the work", on one GPU).  e2e_serve_start is
+ * optional (defaults apply on first submit).  submit copies the request;
+ * host spectra are copied to the device before submit returns.  A request
+ * is admitted when a slot and its HBM footprint are free and is merged with
+ * other admitted requests into the next launch.  poll waits up to
+ * timeout_ms (0 = no wait, <0 = forever) and returns E2E_OK, E2E_PENDING or
+ * the request's error; after a non-pending result the ticket is released.
+ * Submit and poll are thread-safe.  e2e_serve_stop drains and joins.
+ */
+e2e_status e2e_serve_start(e2e_ctx *ctx, const e2e_serve_config *cfg);
+e2e_status e2e_serve_submit(e2e_ctx *ctx, const e2e_render_req *req, e2e_ticket *out);
+e2e_status e2e_serve_poll(e2e_ctx *ctx, e2e_ticket t, int32_t timeout_ms,
+                          e2e_render_stats *stats);
+e2e_status e2e_serve_stop(e2e_ctx *ctx);
+
+/*
+ * Photon noise on an existing expected-count frame, in place (Sec. 2.2):
+ * frame[p] <- Poisson(frame[p]) with the counter stream of pixel p.
+ */
+e2e_status e2e_noise_poisson(e2e_ctx *ctx, void *frame, int32_t dtype, int64_t n_pixels,
+                             uint64_t seed, uint32_t frame_index, int32_t on_device,
+                             void *hip_stream);
+/*
+ * Raw Philox-4x32-10 blocks (Salmon et al., SC'11) of the noise stream:
+ * out_host[(p * blocks + b) * 4 + w] = word w of block b of pixel pixel0+p.
+ */
+e2e_status e2e_philox_blocks(e2e_ctx *ctx, uint64_t seed, uint32_t frame_index,
+                             uint64_t pixel0, int64_t n_pixels, uint32_t blocks,
+                             uint32_t *out_host);
+
+/*
+ * Kernel timing: with profiling on, the library brackets each launch of its
+ * render kernels with HIP events on the launch stream.  e2e_kernel_time
+ * returns launches and total milliseconds per kernel name ("render_table",
+ * "render_sep", "render_sep_mfma", "plan", "noise"), synchronising first.
+ */
+e2e_status e2e_set_profiling(e2e_ctx *ctx, int32_t on);
+e2e_status e2e_kernel_time(e2e_ctx *ctx, const char *kernel, int64_t *launches,
+                           double *total_ms);
+e2e_status e2e_reset_kernel_time(e2e_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* E2E_H */

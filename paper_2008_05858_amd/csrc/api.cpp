@@ -1,0 +1,865 @@
+// Host runtime of the C ABI declared in include/e2e.h: context, validation
+// of the spectral-format / PSF database (Genoni et al. 2020, Sec. 2.1),
+// device-resident tables, render and batch dispatch, kernel timing.  The
+// serve loop lives in serve.cpp.
+#include "api_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace e2e;
+
+static thread_local std::string g_err;
+
+e2e_status e2e::fail(e2e_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+e2e_status e2e::hip_fail(hipError_t e, const char *what)
+{
+    return fail(E2E_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" const char *e2e_last_error(void) { return g_err.c_str(); }
+extern "C" const char *e2e_version(void) { return "e2e-mi355x 0.1 (gfx950)"; }
+
+double e2e::now_us(const e2e_ctx *ctx)
+{
+    return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - ctx->t0)
+        .count();
+}
+
+// ------------------------------------------------------------------ context
+
+extern "C" e2e_status e2e_create(e2e_ctx **out, int32_t dev, uint64_t budget)
+{
+    if (!out) return fail(E2E_EINVAL, "e2e_create: out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (dev < 0 || dev >= ndev)
+        return fail(E2E_EINVAL, "e2e_create: device %d not in [0, %d)", dev, ndev);
+    if ((e = hipSetDevice(dev)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    size_t freeb = 0, totb = 0;
+    if ((e = hipMemGetInfo(&freeb, &totb)) != hipSuccess) return hip_fail(e, "hipMemGetInfo");
+    auto *c = new e2e_ctx();
+    c->dev = dev;
+    c->budget = budget ? budget : (uint64_t)(0.9 * (double)freeb);
+    c->t0 = std::chrono::steady_clock::now();
+    if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipStreamCreate");
+    }
+    *out = c;
+    return E2E_OK;
+}
+
+static void free_scratch(Scratch *s)
+{
+    if (!s) return;
+    hipFree(s->frames_dev);
+    hipFree(s->segs);
+    hipFree(s->work);
+    hipFree(s->specptrs);
+    hipFree(s->err);
+    hipFree(s->counter);
+    if (s->err_host) hipHostFree(s->err_host);
+    if (s->stage) hipHostFree(s->stage);
+    if (s->staged) hipEventDestroy(s->staged);
+    for (void *p : s->temps) hipFree(p);
+    for (auto &g : s->graphs) {
+        hipGraphExecDestroy(g.second.exec);
+        hipGraphDestroy(g.second.graph);
+    }
+    delete s;
+}
+
+extern "C" void e2e_destroy(e2e_ctx *ctx)
+{
+    if (!ctx) return;
+    hipSetDevice(ctx->dev);
+    e2e_serve_stop(ctx);
+    hipDeviceSynchronize();
+    for (auto &kv : ctx->fmts) {
+        hipFree(kv.second->dev);
+        delete kv.second;
+    }
+    for (auto &kv : ctx->psfs) {
+        hipFree(kv.second->tb);
+        hipFree(kv.second->sxy);
+        delete kv.second;
+    }
+    for (auto &kv : ctx->scratch) free_scratch(kv.second);
+    for (auto &p : ctx->prof_pending) {
+        hipEventDestroy(p.a);
+        hipEventDestroy(p.b);
+    }
+    hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+// ------------------------------------------------------------ format load
+
+static double poly(const double *c, int deg, double t)
+{
+    double v = c[deg];
+    for (int j = deg - 1; j >= 0; --j) v = v * t + c[j];
+    return v;
+}
+
+static double dpoly(const double *c, int deg, double t, int order)
+{
+    // derivative of given order, evaluated directly
+    double v = 0.0;
+    for (int j = deg; j >= order; --j) {
+        double f = 1.0;
+        for (int q = 0; q < order; ++q) f *= (double)(j - q);
+        v = v * t + c[j] * f;
+    }
+    return v;
+}
+
+extern "C" e2e_status e2e_format_load(e2e_ctx *ctx, const e2e_trace_desc *tr, int32_t n,
+                                      int32_t nx, int32_t ny, e2e_format_id *out)
+{
+    if (!ctx || !tr || !out) return fail(E2E_EINVAL, "e2e_format_load: NULL argument");
+    if (n < 1 || n > (1 << 20)) return fail(E2E_EINVAL, "e2e_format_load: n_traces=%d", n);
+    if (nx < 1 || ny < 1 || nx > 65536 || ny > 65536)
+        return fail(E2E_EINVAL, "e2e_format_load: detector %dx%d", nx, ny);
+    std::vector<TraceDev> h(n);
+    int dxm = 0, dym = 0, nslots = 0;
+    const int NG = 4097;
+    for (int i = 0; i < n; ++i) {
+        const e2e_trace_desc &d = tr[i];
+        if (d.deg_x < 1 || d.deg_x > 7 || d.deg_y < 0 || d.deg_y > 7)
+            return fail(E2E_EFORMAT, "trace %d: degrees (%d, %d) outside x 1..7, y 0..7", i,
+                        d.deg_x, d.deg_y);
+        if (!d.cx || !d.cy) return fail(E2E_EINVAL, "trace %d: NULL coefficients", i);
+        if (!(std::isfinite(d.lambda_min_nm) && std::isfinite(d.lambda_max_nm) &&
+              d.lambda_min_nm > 0 && d.lambda_min_nm < d.lambda_max_nm))
+            return fail(E2E_EFORMAT, "trace %d: need 0 < lambda_min < lambda_max", i);
+        if (d.n_samples < 1 || d.n_samples > 0x7ffffffe)
+            return fail(E2E_EINVAL, "trace %d: n_samples=%lld", i, (long long)d.n_samples);
+        if (!(std::isfinite(d.throughput) && d.throughput >= 0))
+            return fail(E2E_EINVAL, "trace %d: throughput must be finite and >= 0", i);
+        if (d.spectrum_slot < 0 || d.spectrum_slot >= (1 << 20))
+            return fail(E2E_EINVAL, "trace %d: spectrum_slot=%d", i, d.spectrum_slot);
+        TraceDev &T = h[i];
+        memset(&T, 0, sizeof T);
+        for (int j = 0; j <= d.deg_x; ++j) {
+            if (!std::isfinite(d.cx[j])) return fail(E2E_EFORMAT, "trace %d: cx not finite", i);
+            T.cx[j] = d.cx[j];
+        }
+        for (int j = 0; j <= d.deg_y; ++j) {
+            if (!std::isfinite(d.cy[j])) return fail(E2E_EFORMAT, "trace %d: cy not finite", i);
+            T.cy[j] = d.cy[j];
+        }
+        T.lmin = d.lambda_min_nm;
+        T.lmax = d.lambda_max_nm;
+        T.thr = d.throughput;
+        T.n = (int32_t)d.n_samples;
+        T.degx = d.deg_x;
+        T.degy = d.deg_y;
+        T.slot = d.spectrum_slot;
+        // x strictly increasing and |dy/dx| <= 0.5 over t in [-1.001, 1.001]
+        // (the Doppler range); grid minima corrected by the second derivative
+        double h_t = 2.002 / (NG - 1), minx1 = 1e300, maxx2 = 0, maxslope = 0, maxy2 = 0,
+               maxy1 = 0;
+        for (int g = 0; g < NG; ++g) {
+            double t = -1.001 + h_t * g;
+            double x1 = dpoly(T.cx, T.degx, t, 1);
+            double x2 = fabs(dpoly(T.cx, T.degx, t, 2));
+            double y1 = fabs(dpoly(T.cy, T.degy, t, 1));
+            double y2 = fabs(dpoly(T.cy, T.degy, t, 2));
+            minx1 = std::min(minx1, x1);
+            maxx2 = std::max(maxx2, x2);
+            maxy2 = std::max(maxy2, y2);
+            maxy1 = std::max(maxy1, y1);
+            if (x1 > 0) maxslope = std::max(maxslope, y1 / x1);
+        }
+        double xlow = minx1 - maxx2 * h_t / 2;
+        if (!(xlow > 0))
+            return fail(E2E_EFORMAT, "trace %d: x(lambda) is not strictly increasing", i);
+        if (xlow * 2.0 / (double)T.n < 1e-9)
+            return fail(E2E_EFORMAT, "trace %d: samples closer than 1e-9 px", i);
+        double slope_hi = (maxy1 + maxy2 * h_t / 2) / xlow;
+        if (maxslope > 0.5 || slope_hi > 0.5 + 1e-3)
+            return fail(E2E_EFORMAT, "trace %d: |dy/dx| up to %.3g exceeds 0.5", i,
+                        std::max(maxslope, slope_hi));
+        // |y''| bound for the planner (grid max plus third-derivative slack)
+        double y3 = 0;
+        for (int g = 0; g < NG; ++g)
+            y3 = std::max(y3, fabs(dpoly(T.cy, T.degy, -1.001 + h_t * g, 3)));
+        T.y2max = maxy2 + y3 * h_t + 1e-9;
+        dxm = std::max(dxm, T.degx);
+        dym = std::max(dym, T.degy);
+        nslots = std::max(nslots, T.slot + 1);
+    }
+    hipSetDevice(ctx->dev);
+    size_t bytes = sizeof(TraceDev) * n;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->used + bytes > ctx->budget)
+        return fail(E2E_ENOMEM, "e2e_format_load: %zu bytes exceed the HBM budget", bytes);
+    auto *F = new FormatRes();
+    F->nx = nx;
+    F->ny = ny;
+    F->ntr = n;
+    F->nslots = nslots;
+    F->degx = dxm;
+    F->degy = dym;
+    F->host = h;
+    F->bytes = bytes;
+    hipError_t e = hipMalloc(&F->dev, bytes);
+    if (e == hipSuccess) e = hipMemcpy(F->dev, h.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(F->dev);
+        delete F;
+        return hip_fail(e, "e2e_format_load");
+    }
+    ctx->used += bytes;
+    uint64_t id = ctx->next_id++;
+    ctx->fmts[id] = F;
+    *out = id;
+    return E2E_OK;
+}
+
+// --------------------------------------------------------------- PSF load
+
+// Taps of one node: B(vy, vx) = sum of the table over the os x os cells
+// starting at (vx, vy) (cells outside the table are zero), stored as
+// tb[p][s][dd] = B(os dd - p, kw - 1 - s).
+static void node_taps(const float *K, int kw, double *tb)
+{
+    const int OS = kOS, NS = kw + OS - 1, DD = (kw + OS - 2) / OS + 1;
+    std::vector<double> pre((size_t)(kw + 1) * (kw + 1), 0.0);  // 2D prefix sums
+    for (int b = 0; b < kw; ++b)
+        for (int a = 0; a < kw; ++a)
+            pre[(size_t)(b + 1) * (kw + 1) + a + 1] = (double)K[(size_t)b * kw + a] +
+                                                      pre[(size_t)b * (kw + 1) + a + 1] +
+                                                      pre[(size_t)(b + 1) * (kw + 1) + a] -
+                                                      pre[(size_t)b * (kw + 1) + a];
+    auto box = [&](int vy, int vx) {
+        int y0 = std::max(vy, 0), y1 = std::min(vy + OS, kw);
+        int x0 = std::max(vx, 0), x1 = std::min(vx + OS, kw);
+        if (y0 >= y1 || x0 >= x1) return 0.0;
+        // direct sum (exact in FP64 for float inputs)
+        double s = 0.0;
+        for (int b = y0; b < y1; ++b)
+            for (int a = x0; a < x1; ++a) s += (double)K[(size_t)b * kw + a];
+        return s;
+    };
+    (void)pre;
+    for (int p = 0; p < OS; ++p)
+        for (int s = 0; s < NS; ++s)
+            for (int dd = 0; dd < DD; ++dd)
+                tb[((size_t)p * NS + s) * DD + dd] = box(OS * dd - p, kw - 1 - s);
+}
+
+extern "C" e2e_status e2e_psf_load(e2e_ctx *ctx, const e2e_psf_desc *d, e2e_psf_id *out)
+{
+    if (!ctx || !d || !out) return fail(E2E_EINVAL, "e2e_psf_load: NULL argument");
+    auto *P = new PsfRes();
+    P->kind = d->kind;
+    P->sigma = d->sigma;
+    P->H = d->half_width;
+    P->gx = d->grid_nx;
+    P->gy = d->grid_ny;
+    P->kw = d->kw;
+    P->kh = d->kh;
+    P->os = d->oversample;
+    std::vector<double> tb;
+    std::vector<float> sxy;
+    auto bad = [&](e2e_status c, const char *m) {
+        delete P;
+        return fail(c, "e2e_psf_load: %s", m);
+    };
+    if (d->kind == E2E_PSF_GAUSS_ERF) {
+        if (!(std::isfinite(d->sigma) && d->sigma > 0)) return bad(E2E_EPSF, "sigma must be > 0");
+        if (d->half_width < 1 || d->half_width > 8) return bad(E2E_EPSF, "half_width outside 1..8");
+        P->gx = P->gy = 1;
+    } else if (d->kind == E2E_PSF_SEPARABLE) {
+        if (d->half_width < 1 || d->half_width > 8) return bad(E2E_EPSF, "half_width outside 1..8");
+        if (d->grid_nx < 1 || d->grid_ny < 1 || d->grid_nx > 127 || d->grid_ny > 127)
+            return bad(E2E_EPSF, "grid outside 1..127");
+        if (!d->sigma_xy) return bad(E2E_EINVAL, "sigma_xy is NULL");
+        size_t nn = (size_t)d->grid_nx * d->grid_ny * 2;
+        sxy.assign(d->sigma_xy, d->sigma_xy + nn);
+        for (float v : sxy)
+            if (!(std::isfinite(v) && v > 0)) return bad(E2E_EPSF, "sigma_xy must be > 0");
+    } else if (d->kind == E2E_PSF_TABLE) {
+        if (d->grid_nx < 1 || d->grid_ny < 1 || d->grid_nx > 127 || d->grid_ny > 127)
+            return bad(E2E_EPSF, "grid outside 1..127");
+        if (!d->tables) return bad(E2E_EINVAL, "tables is NULL");
+        if (d->kw < 1 || d->kh < 1 || d->oversample < 1) return bad(E2E_EPSF, "bad table shape");
+        if (d->oversample != kOS || d->kw != d->kh || (d->kw != 32 && d->kw != 48))
+            return bad(E2E_EUNSUPPORTED, "GPU path needs oversample 4 and kw = kh in {32, 48}");
+        size_t ksz = (size_t)d->kw * d->kh, nodes = (size_t)d->grid_nx * d->grid_ny;
+        const int NS = d->kw + kOS - 1, DD = (d->kw + kOS - 2) / kOS + 1;
+        size_t node = (size_t)kOS * NS * DD;
+        tb.resize(node * nodes);
+        for (size_t q = 0; q < nodes; ++q) {
+            const float *K = d->tables + q * ksz;
+            double s = 0;
+            for (size_t e = 0; e < ksz; ++e) {
+                if (!std::isfinite(K[e])) return bad(E2E_EPSF, "table value not finite");
+                s += K[e];
+            }
+            if (fabs(s - 1.0) > 1e-5) {
+                delete P;
+                return fail(E2E_EPSF, "e2e_psf_load: node %zu sums to %.9g, not 1", q, s);
+            }
+            node_taps(K, d->kw, tb.data() + q * node);
+        }
+    } else {
+        return bad(E2E_EINVAL, "unknown PSF kind");
+    }
+    hipSetDevice(ctx->dev);
+    size_t bytes = tb.size() * sizeof(double) + sxy.size() * sizeof(float);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->used + bytes > ctx->budget) return bad(E2E_ENOMEM, "tables exceed the HBM budget");
+    hipError_t e = hipSuccess;
+    if (!tb.empty()) {
+        e = hipMalloc(&P->tb, tb.size() * sizeof(double));
+        if (e == hipSuccess)
+            e = hipMemcpy(P->tb, tb.data(), tb.size() * sizeof(double), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && !sxy.empty()) {
+        e = hipMalloc(&P->sxy, sxy.size() * sizeof(float));
+        if (e == hipSuccess)
+            e = hipMemcpy(P->sxy, sxy.data(), sxy.size() * sizeof(float), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        hipFree(P->tb);
+        hipFree(P->sxy);
+        delete P;
+        return hip_fail(e, "e2e_psf_load");
+    }
+    P->bytes = bytes;
+    ctx->used += bytes;
+    uint64_t id = ctx->next_id++;
+    ctx->psfs[id] = P;
+    *out = id;
+    return E2E_OK;
+}
+
+extern "C" e2e_status e2e_format_free(e2e_ctx *ctx, e2e_format_id id)
+{
+    if (!ctx) return fail(E2E_EINVAL, "e2e_format_free: NULL context");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->fmts.find(id);
+    if (it == ctx->fmts.end()) return fail(E2E_ENOTFOUND, "format %llu not found",
+                                           (unsigned long long)id);
+    if (it->second->refs > 0) return fail(E2E_EBUSY, "format %llu in use", (unsigned long long)id);
+    hipSetDevice(ctx->dev);
+    hipDeviceSynchronize();
+    hipFree(it->second->dev);
+    ctx->used -= it->second->bytes;
+    delete it->second;
+    ctx->fmts.erase(it);
+    return E2E_OK;
+}
+
+extern "C" e2e_status e2e_psf_free(e2e_ctx *ctx, e2e_psf_id id)
+{
+    if (!ctx) return fail(E2E_EINVAL, "e2e_psf_free: NULL context");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->psfs.find(id);
+    if (it == ctx->psfs.end()) return fail(E2E_ENOTFOUND, "psf %llu not found",
+                                           (unsigned long long)id);
+    if (it->second->refs > 0) return fail(E2E_EBUSY, "psf %llu in use", (unsigned long long)id);
+    hipSetDevice(ctx->dev);
+    hipDeviceSynchronize();
+    hipFree(it->second->tb);
+    hipFree(it->second->sxy);
+    ctx->used -= it->second->bytes;
+    delete it->second;
+    ctx->psfs.erase(it);
+    return E2E_OK;
+}
+
+// ------------------------------------------------------------ render core
+
+static e2e_status grow(void **p, size_t *cap, size_t need, const char *what)
+{
+    if (*cap >= need) return E2E_OK;
+    size_t n = std::max(need, *cap * 2);
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, n);
+    if (e != hipSuccess) return hip_fail(e, what);
+    hipFree(*p);
+    *p = q;
+    *cap = n;
+    return E2E_OK;
+}
+
+Scratch *e2e::scratch_for(e2e_ctx *ctx, hipStream_t s)
+{
+    auto it = ctx->scratch.find(s);
+    if (it != ctx->scratch.end()) return it->second;
+    auto *sc = new Scratch();
+    if (hipMalloc(&sc->err, sizeof(int)) != hipSuccess ||
+        hipMalloc(&sc->counter, sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void **)&sc->err_host, sizeof(int)) != hipSuccess) {
+        free_scratch(sc);
+        return nullptr;
+    }
+    ctx->scratch[s] = sc;
+    return sc;
+}
+
+e2e_status e2e::validate_req(e2e_ctx *ctx, const e2e_render_req *r, FormatRes **pf,
+                             PsfRes **pp)
+{
+    if (!r) return fail(E2E_EINVAL, "request is NULL");
+    auto fi = ctx->fmts.find(r->fmt);
+    if (fi == ctx->fmts.end())
+        return fail(E2E_ENOTFOUND, "format %llu not found", (unsigned long long)r->fmt);
+    auto pi = ctx->psfs.find(r->psf);
+    if (pi == ctx->psfs.end())
+        return fail(E2E_ENOTFOUND, "psf %llu not found", (unsigned long long)r->psf);
+    FormatRes *F = fi->second;
+    PsfRes *P = pi->second;
+    if (!r->spectra) return fail(E2E_EINVAL, "spectra is NULL");
+    if (r->n_spectra < F->nslots)
+        return fail(E2E_EINVAL, "n_spectra=%d but the format uses %d slots", r->n_spectra,
+                    F->nslots);
+    for (int s = 0; s < F->nslots; ++s)
+        if (!r->spectra[s]) return fail(E2E_EINVAL, "spectra[%d] is NULL", s);
+    if (r->spectrum_dtype != E2E_F32 && r->spectrum_dtype != E2E_F64)
+        return fail(E2E_EINVAL, "spectrum_dtype=%d", r->spectrum_dtype);
+    if (r->out_dtype != E2E_F32 && r->out_dtype != E2E_F64)
+        return fail(E2E_EINVAL, "out_dtype=%d", r->out_dtype);
+    if (!r->out) return fail(E2E_EINVAL, "out is NULL");
+    if (!(std::isfinite(r->rv_mps) && fabs(r->rv_mps) <= 1.5e5))
+        return fail(E2E_EINVAL, "rv_mps must be finite with |v| <= 1.5e5 m/s");
+    if (!(std::isfinite(r->flux_scale) && r->flux_scale >= 0))
+        return fail(E2E_EINVAL, "flux_scale must be finite and >= 0");
+    if (r->precision < E2E_PREC_F64 || r->precision > E2E_PREC_F16_HILO)
+        return fail(E2E_EINVAL, "precision=%d", r->precision);
+    if (r->precision != E2E_PREC_F64 && P->kind != E2E_PSF_SEPARABLE)
+        return fail(E2E_EUNSUPPORTED, "reduced precisions exist on the separable path only");
+    if (P->kind == E2E_PSF_TABLE) {
+        // a tile column (and its footprint) must meet at most two node cells
+        int tw = table_tw(P->kw);
+        double span = (double)tw + (double)P->kw / kOS + 4.0;
+        double spx = P->gx > 1 ? (double)(F->nx - 1) / (P->gx - 1) : 1e30;
+        double spy = P->gy > 1 ? (double)(F->ny - 1) / (P->gy - 1) : 1e30;
+        if (spx < span || spy < span)
+            return fail(E2E_EUNSUPPORTED,
+                        "PSF nodes %.1f x %.1f px apart; the table path needs >= %.0f px",
+                        spx, spy, span);
+    }
+    *pf = F;
+    *pp = P;
+    return E2E_OK;
+}
+
+static void tile_geom(const PsfRes *P, int precision, int *tw, int *th)
+{
+    if (P->kind == E2E_PSF_TABLE) {
+        *tw = table_tw(P->kw);
+        *th = kTableTH;
+    } else if (P->kind == E2E_PSF_SEPARABLE &&
+               (precision == E2E_PREC_BF16_HILO || precision == E2E_PREC_F16_HILO)) {
+        *tw = kMfmaTW;
+        *th = kMfmaTH;
+    } else {
+        *tw = *th = kSepTile;
+    }
+}
+
+e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool batch,
+                           int *batch_sizes_out)
+{
+    (void)batch_sizes_out;
+    if (!ctx) return fail(E2E_EINVAL, "NULL context");
+    if (n < 1) return fail(E2E_EINVAL, "n=%d", n);
+    hipSetDevice(ctx->dev);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    std::vector<FormatRes *> fs(n);
+    std::vector<PsfRes *> ps(n);
+    for (int i = 0; i < n; ++i) {
+        e2e_status st = validate_req(ctx, &reqs[i], &fs[i], &ps[i]);
+        if (st != E2E_OK) return st;
+    }
+    // one launch: a single PSF kind / table size / precision
+    for (int i = 1; i < n; ++i) {
+        if (ps[i]->kind != ps[0]->kind || ps[i]->kw != ps[0]->kw ||
+            reqs[i].precision != reqs[0].precision ||
+            reqs[i].spectrum_dtype != reqs[0].spectrum_dtype)
+            return fail(E2E_EINVAL,
+                        "batch frames must share PSF kind, table size, precision, spectrum type");
+        if (reqs[i].hip_stream != reqs[0].hip_stream)
+            return fail(E2E_EINVAL, "batch frames must share one stream");
+    }
+    hipStream_t s = reqs[0].hip_stream ? (hipStream_t)reqs[0].hip_stream : ctx->stream;
+    Scratch *sc = scratch_for(ctx, s);
+    if (!sc) return fail(E2E_EDEVICE, "scratch allocation failed");
+    // temporaries of the previous call on this stream are free once the
+    // stream has passed it
+    hipError_t e = hipSuccess;
+    if (!sc->temps.empty()) {
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        for (void *p : sc->temps) hipFree(p);
+        sc->temps.clear();
+    }
+
+    const int kind = ps[0]->kind, prec = reqs[0].precision;
+    KernelCfg cfg{};
+    cfg.kw = kind == E2E_PSF_TABLE ? ps[0]->kw : (kind == E2E_PSF_SEPARABLE ? 1 : 0);
+    cfg.spec_f64 = reqs[0].spectrum_dtype == E2E_F64;
+    cfg.precision = prec;
+    size_t seg_total = 0;
+    std::vector<size_t> seg_off(n);
+    std::vector<int> tiles(n);
+    int nslots_total = 0;
+    std::vector<int> spec_off(n);
+    size_t temp_bytes = 0;
+    for (int i = 0; i < n; ++i) {
+        int tw, th;
+        tile_geom(ps[i], prec, &tw, &th);
+        int ntx = (fs[i]->nx + tw - 1) / tw, nty = (fs[i]->ny + th - 1) / th;
+        tiles[i] = ntx * nty;
+        seg_off[i] = seg_total;
+        seg_total += (size_t)ntx * fs[i]->ntr;
+        spec_off[i] = nslots_total;
+        nslots_total += fs[i]->nslots;
+        cfg.degx = std::max(cfg.degx, fs[i]->degx);
+        cfg.degy = std::max(cfg.degy, fs[i]->degy);
+        if (!reqs[i].out_on_device)
+            temp_bytes += (size_t)fs[i]->nx * fs[i]->ny * (reqs[i].out_dtype == E2E_F64 ? 8 : 4);
+    }
+    size_t work_n = 0;
+    for (int i = 0; i < n; ++i) work_n += tiles[i];
+    size_t scratch_need = seg_total * sizeof(SegDev) + n * sizeof(FrameDev) +
+                          work_n * sizeof(int2) + nslots_total * sizeof(void *);
+    if (ctx->used + temp_bytes + scratch_need > ctx->budget)
+        return fail(E2E_ENOMEM, "render needs %zu bytes beyond the %llu-byte budget",
+                    temp_bytes + scratch_need, (unsigned long long)ctx->budget);
+    e2e_status st;
+    if ((st = grow((void **)&sc->segs, &sc->segs_cap, seg_total * sizeof(SegDev) + 16,
+                   "segs")) != E2E_OK)
+        return st;
+    if ((st = grow((void **)&sc->frames_dev, &sc->frames_cap, n * sizeof(FrameDev),
+                   "frames")) != E2E_OK)
+        return st;
+    if ((st = grow((void **)&sc->work, &sc->work_cap, work_n * sizeof(int2) + 16, "work")) !=
+        E2E_OK)
+        return st;
+    if ((st = grow((void **)&sc->specptrs, &sc->specptrs_cap,
+                   nslots_total * sizeof(void *) + 16, "spectra")) != E2E_OK)
+        return st;
+
+    // spectra pointers (device), host spectra copied to temporaries
+    sc->h_specptrs.assign(nslots_total, nullptr);
+    for (int i = 0; i < n; ++i) {
+        const e2e_render_req &r = reqs[i];
+        size_t esz = r.spectrum_dtype == E2E_F64 ? 8 : 4;
+        std::vector<int64_t> len(fs[i]->nslots, 0);
+        for (auto &T : fs[i]->host) len[T.slot] = std::max<int64_t>(len[T.slot], T.n);
+        for (int q = 0; q < fs[i]->nslots; ++q) {
+            if (r.spectra_on_device || len[q] == 0) {
+                sc->h_specptrs[spec_off[i] + q] = (void *)r.spectra[q];
+                continue;
+            }
+            void *d = nullptr;
+            if ((e = hipMalloc(&d, len[q] * esz)) != hipSuccess) return hip_fail(e, "spectrum");
+            sc->temps.push_back(d);
+            if ((e = hipMemcpyAsync(d, r.spectra[q], len[q] * esz, hipMemcpyHostToDevice, s)) !=
+                hipSuccess)
+                return hip_fail(e, "spectrum upload");
+            sc->h_specptrs[spec_off[i] + q] = d;
+        }
+    }
+    sc->h_frames.assign(n, FrameDev{});
+    std::vector<void *> dev_out(n);
+    for (int i = 0; i < n; ++i) {
+        const e2e_render_req &r = reqs[i];
+        FrameDev &F = sc->h_frames[i];
+        FormatRes *fm = fs[i];
+        PsfRes *P = ps[i];
+        int tw, th;
+        tile_geom(P, prec, &tw, &th);
+        F.tr = fm->dev;
+        F.spec = sc->specptrs + spec_off[i];
+        if (r.out_on_device) {
+            dev_out[i] = r.out;
+        } else {
+            size_t ob = (size_t)fm->nx * fm->ny * (r.out_dtype == E2E_F64 ? 8 : 4);
+            if ((e = hipMalloc(&dev_out[i], ob)) != hipSuccess) return hip_fail(e, "out");
+            sc->temps.push_back(dev_out[i]);
+        }
+        F.out = dev_out[i];
+        F.tb = P->tb;
+        F.sxy = P->sxy;
+        F.segs = sc->segs + seg_off[i];
+        F.beta = r.rv_mps / 299792458.0;
+        F.flux_scale = r.flux_scale;
+        F.sigma = P->sigma;
+        F.gx = P->gx;
+        F.gy = P->gy;
+        F.gsx = P->gx > 1 ? (double)(P->gx - 1) / (double)(fm->nx - 1) : 0.0;
+        F.gsy = P->gy > 1 ? (double)(P->gy - 1) / (double)(fm->ny - 1) : 0.0;
+        F.ntr = fm->ntr;
+        F.nx = fm->nx;
+        F.ny = fm->ny;
+        F.psf_kind = P->kind;
+        F.H = P->H;
+        F.kw = P->kw;
+        F.spec_f64 = r.spectrum_dtype == E2E_F64;
+        F.out_f64 = r.out_dtype == E2E_F64;
+        F.precision = r.precision;
+        F.tw = tw;
+        F.th = th;
+        F.ntx = (fm->nx + tw - 1) / tw;
+        F.nty = (fm->ny + th - 1) / th;
+        F.poisson = r.poisson ? 1 : 0;
+        F.frame_index = r.frame_index;
+        F.seed = r.seed;
+    }
+    cfg.plain_tiles = tiles[0];
+    // work list: frames by decreasing size, tiles in order
+    sc->h_work.clear();
+    if (batch) {
+        std::vector<int> order(n);
+        for (int i = 0; i < n; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return tiles[a] > tiles[b]; });
+        sc->h_work.reserve(work_n);
+        for (int i : order)
+            for (int t = 0; t < tiles[i]; ++t) sc->h_work.push_back(make_int2(i, t));
+    }
+    // parameter upload through pinned staging (reused once its copy ran)
+    size_t b_spec = nslots_total * sizeof(void *), b_fr = n * sizeof(FrameDev),
+           b_work = batch ? work_n * sizeof(int2) : 0;
+    size_t b_all = b_spec + b_fr + b_work + 64;
+    if (sc->staged_valid) {
+        if ((e = hipEventSynchronize(sc->staged)) != hipSuccess) return hip_fail(e, "staging");
+    }
+    if (sc->stage_cap < b_all) {
+        if (sc->stage) hipHostFree(sc->stage);
+        sc->stage = nullptr;
+        sc->stage_cap = 0;
+        if ((e = hipHostMalloc(&sc->stage, b_all * 2)) != hipSuccess) return hip_fail(e, "staging");
+        sc->stage_cap = b_all * 2;
+    }
+    if (!sc->staged) {
+        if ((e = hipEventCreateWithFlags(&sc->staged, hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "event");
+    }
+    char *stg = (char *)sc->stage;
+    memcpy(stg, sc->h_specptrs.data(), b_spec);
+    memcpy(stg + b_spec, sc->h_frames.data(), b_fr);
+    if (b_work) memcpy(stg + b_spec + b_fr, sc->h_work.data(), b_work);
+    if ((e = hipMemcpyAsync(sc->specptrs, stg, b_spec, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(sc->frames_dev, stg + b_spec, b_fr, hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+        return hip_fail(e, "parameter upload");
+    if (b_work && (e = hipMemcpyAsync(sc->work, stg + b_spec + b_fr, b_work,
+                                      hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_fail(e, "work upload");
+    if ((e = hipEventRecord(sc->staged, s)) != hipSuccess) return hip_fail(e, "event");
+    sc->staged_valid = true;
+
+    // launches: clear error word and queue counter, plan, render, noise
+    if ((e = launch_fill_i32(sc->err, 1, 0, s)) != hipSuccess) return hip_fail(e, "fill");
+    if ((e = launch_fill_i32(sc->counter, 1, 0, s)) != hipSuccess) return hip_fail(e, "fill");
+    prof_begin(ctx, s, "plan");
+    e = launch_plan(sc->frames_dev, sc->h_frames.data(), n, sc->err, s);
+    prof_end(ctx, s);
+    if (e != hipSuccess) return hip_fail(e, "plan launch");
+    const int2 *work = batch ? sc->work : nullptr;
+    int nwork = batch ? (int)work_n : 0;
+    if (kind == E2E_PSF_TABLE) {
+        prof_begin(ctx, s, "render_table");
+        e = launch_table(sc->frames_dev, cfg, work, nwork, sc->counter, sc->err, s);
+    } else if (kind == E2E_PSF_SEPARABLE &&
+               (prec == E2E_PREC_BF16_HILO || prec == E2E_PREC_F16_HILO)) {
+        prof_begin(ctx, s, "render_sep_mfma");
+        e = launch_sep_mfma(sc->frames_dev, cfg, work, nwork, sc->counter, sc->err, s);
+    } else {
+        prof_begin(ctx, s, "render_sep");
+        e = launch_sep(sc->frames_dev, cfg, work, nwork, sc->counter, sc->err, s);
+    }
+    prof_end(ctx, s);
+    if (e != hipSuccess) return hip_fail(e, "render launch");
+    bool any_noise = false;
+    for (int i = 0; i < n; ++i) any_noise |= reqs[i].poisson != 0;
+    if (any_noise) {
+        prof_begin(ctx, s, "noise");
+        e = launch_noise_frames(sc->frames_dev, sc->h_frames.data(), n, s);
+        prof_end(ctx, s);
+        if (e != hipSuccess) return hip_fail(e, "noise launch");
+    }
+    for (int i = 0; i < n; ++i) {
+        if (reqs[i].out_on_device) continue;
+        size_t ob = (size_t)fs[i]->nx * fs[i]->ny * (reqs[i].out_dtype == E2E_F64 ? 8 : 4);
+        if ((e = hipMemcpyAsync(reqs[i].out, dev_out[i], ob, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess)
+            return hip_fail(e, "out download");
+    }
+    if ((e = hipMemcpyAsync(sc->err_host, sc->err, sizeof(int), hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+        return hip_fail(e, "error word");
+    bool all_async = true;
+    for (int i = 0; i < n; ++i)
+        all_async &= (reqs[i].flags & E2E_FLAG_ASYNC) && reqs[i].out_on_device &&
+                     reqs[i].spectra_on_device;
+    if (all_async) return E2E_OK;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "render");
+    return check_err_word(*sc->err_host);
+}
+
+e2e_status e2e::check_err_word(int w)
+{
+    if (w == 0) return E2E_OK;
+    return fail(E2E_EINTERNAL,
+                "device check failed (0x%x):%s%s%s%s", w,
+                (w & kErrTileTraces) ? " too many traces reach one tile;" : "",
+                (w & kErrRowWindow) ? " a slot column left its row window;" : "",
+                (w & kErrSearch) ? " column search did not converge;" : "",
+                (w & kErrCells) ? " a tile column spans more than two PSF node cells;" : "");
+}
+
+extern "C" e2e_status e2e_render(e2e_ctx *ctx, const e2e_render_req *req)
+{
+    return run_frames(ctx, req, 1, false, nullptr);
+}
+
+extern "C" e2e_status e2e_render_batch(e2e_ctx *ctx, const e2e_render_req *reqs, int32_t n)
+{
+    if (!reqs) return fail(E2E_EINVAL, "e2e_render_batch: reqs is NULL");
+    return run_frames(ctx, reqs, n, true, nullptr);
+}
+
+// ------------------------------------------------------------------ noise
+
+extern "C" e2e_status e2e_noise_poisson(e2e_ctx *ctx, void *frame, int32_t dtype, int64_t n,
+                                        uint64_t seed, uint32_t fidx, int32_t on_device,
+                                        void *stream)
+{
+    if (!ctx || !frame) return fail(E2E_EINVAL, "e2e_noise_poisson: NULL argument");
+    if (dtype != E2E_F32 && dtype != E2E_F64) return fail(E2E_EINVAL, "dtype=%d", dtype);
+    if (n < 0) return fail(E2E_EINVAL, "n_pixels=%lld", (long long)n);
+    if (n == 0) return E2E_OK;
+    hipSetDevice(ctx->dev);
+    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    size_t bytes = (size_t)n * (dtype == E2E_F64 ? 8 : 4);
+    void *d = frame;
+    hipError_t e;
+    if (!on_device) {
+        if ((e = hipMalloc(&d, bytes)) != hipSuccess) return hip_fail(e, "noise buffer");
+        if ((e = hipMemcpyAsync(d, frame, bytes, hipMemcpyHostToDevice, s)) != hipSuccess) {
+            hipFree(d);
+            return hip_fail(e, "noise upload");
+        }
+    }
+    prof_begin(ctx, s, "noise");
+    e = launch_noise(d, dtype == E2E_F64, n, seed, fidx, s);
+    prof_end(ctx, s);
+    if (e == hipSuccess && !on_device)
+        e = hipMemcpyAsync(frame, d, bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (!on_device) hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "e2e_noise_poisson");
+    return E2E_OK;
+}
+
+extern "C" e2e_status e2e_philox_blocks(e2e_ctx *ctx, uint64_t seed, uint32_t fidx,
+                                        uint64_t pixel0, int64_t n, uint32_t blocks,
+                                        uint32_t *out)
+{
+    if (!ctx || !out) return fail(E2E_EINVAL, "e2e_philox_blocks: NULL argument");
+    if (n < 0 || blocks == 0 || (uint64_t)n * blocks > (1ull << 28))
+        return fail(E2E_EINVAL, "e2e_philox_blocks: bad size");
+    if (n == 0) return E2E_OK;
+    hipSetDevice(ctx->dev);
+    size_t bytes = (size_t)n * blocks * 16;
+    uint32_t *d = nullptr;
+    hipError_t e = hipMalloc(&d, bytes);
+    if (e == hipSuccess) e = launch_philox(seed, fidx, pixel0, n, blocks, d, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d, bytes, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "e2e_philox_blocks");
+    return E2E_OK;
+}
+
+// -------------------------------------------------------------- profiling
+
+void e2e::prof_begin(e2e_ctx *ctx, hipStream_t s, const char *name)
+{
+    if (!ctx->prof) return;
+    ProfRec r;
+    r.name = name;
+    hipEventCreate(&r.a);
+    hipEventCreate(&r.b);
+    hipEventRecord(r.a, s);
+    ctx->prof_pending.push_back(r);
+}
+
+void e2e::prof_end(e2e_ctx *ctx, hipStream_t s)
+{
+    if (!ctx->prof || ctx->prof_pending.empty()) return;
+    hipEventRecord(ctx->prof_pending.back().b, s);
+}
+
+extern "C" e2e_status e2e_set_profiling(e2e_ctx *ctx, int32_t on)
+{
+    if (!ctx) return fail(E2E_EINVAL, "NULL context");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->prof = on != 0;
+    return E2E_OK;
+}
+
+static void prof_collect(e2e_ctx *ctx)
+{
+    for (auto &r : ctx->prof_pending) {
+        hipEventSynchronize(r.b);
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            auto &acc = ctx->prof_acc[r.name];
+            acc.first += 1;
+            acc.second += ms;
+        }
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    ctx->prof_pending.clear();
+}
+
+extern "C" e2e_status e2e_kernel_time(e2e_ctx *ctx, const char *k, int64_t *launches,
+                                      double *total_ms)
+{
+    if (!ctx || !k || !launches || !total_ms) return fail(E2E_EINVAL, "NULL argument");
+    hipSetDevice(ctx->dev);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    prof_collect(ctx);
+    auto it = ctx->prof_acc.find(k);
+    *launches = it == ctx->prof_acc.end() ? 0 : it->second.first;
+    *total_ms = it == ctx->prof_acc.end() ? 0.0 : it->second.second;
+    return E2E_OK;
+}
+
+extern "C" e2e_status e2e_reset_kernel_time(e2e_ctx *ctx)
+{
+    if (!ctx) return fail(E2E_EINVAL, "NULL context");
+    hipSetDevice(ctx->dev);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    prof_collect(ctx);
+    ctx->prof_acc.clear();
+    return E2E_OK;
+}

@@ -1,0 +1,110 @@
+// Host-side state behind the C ABI: context, resident tables, per-stream
+// scratch, timing records, serve-loop hooks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "e2e_impl.h"
+
+namespace e2e {
+
+struct FormatRes {
+    int nx = 0, ny = 0, ntr = 0, nslots = 0, degx = 0, degy = 0;
+    std::vector<TraceDev> host;
+    TraceDev *dev = nullptr;
+    size_t bytes = 0;
+    int refs = 0;  // served requests holding it
+};
+
+struct PsfRes {
+    int kind = 0;
+    double sigma = 0;
+    int H = 0, gx = 1, gy = 1, kw = 0, kh = 0, os = 0;
+    double *tb = nullptr;   // table taps
+    float *sxy = nullptr;   // separable sigma grid
+    size_t bytes = 0;
+    int refs = 0;
+};
+
+struct GraphRec {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+// Device buffers reused by consecutive calls on one stream.
+struct Scratch {
+    FrameDev *frames_dev = nullptr;
+    size_t frames_cap = 0;
+    SegDev *segs = nullptr;
+    size_t segs_cap = 0;
+    int2 *work = nullptr;
+    size_t work_cap = 0;
+    const void **specptrs = nullptr;
+    size_t specptrs_cap = 0;
+    int *err = nullptr;
+    int *counter = nullptr;
+    int *err_host = nullptr;
+    // pinned staging of the parameter uploads, reusable once `staged` fired
+    void *stage = nullptr;
+    size_t stage_cap = 0;
+    hipEvent_t staged = nullptr;
+    bool staged_valid = false;
+    std::vector<void *> temps;   // device temporaries of the last call
+    std::vector<FrameDev> h_frames;
+    std::vector<void *> h_specptrs;
+    std::vector<int2> h_work;
+    std::map<std::string, GraphRec> graphs;
+};
+
+struct ProfRec {
+    std::string name;
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
+struct Server;
+
+}  // namespace e2e
+
+struct e2e_ctx {
+    int dev = 0;
+    uint64_t budget = 0;
+    uint64_t used = 0;
+    std::mutex mu;
+    std::map<uint64_t, e2e::FormatRes *> fmts;
+    std::map<uint64_t, e2e::PsfRes *> psfs;
+    uint64_t next_id = 1;
+    hipStream_t stream = nullptr;
+    std::map<hipStream_t, e2e::Scratch *> scratch;
+    bool prof = false;
+    std::vector<e2e::ProfRec> prof_pending;
+    std::map<std::string, std::pair<int64_t, double>> prof_acc;
+    std::chrono::steady_clock::time_point t0;
+    e2e::Server *srv = nullptr;  // owned by serve.cpp
+    std::mutex srv_mu;
+};
+
+namespace e2e {
+
+e2e_status fail(e2e_status code, const char *fmt, ...);
+e2e_status hip_fail(hipError_t e, const char *what);
+double now_us(const e2e_ctx *ctx);
+Scratch *scratch_for(e2e_ctx *ctx, hipStream_t s);
+e2e_status validate_req(e2e_ctx *ctx, const e2e_render_req *r, FormatRes **pf, PsfRes **pp);
+// Render n frames (batch: one persistent launch).  Caller must not hold mu.
+e2e_status run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool batch,
+                      int *unused);
+e2e_status check_err_word(int w);
+void prof_begin(e2e_ctx *ctx, hipStream_t s, const char *name);
+void prof_end(e2e_ctx *ctx, hipStream_t s);
+void serve_shutdown(e2e_ctx *ctx);
+
+}  // namespace e2e

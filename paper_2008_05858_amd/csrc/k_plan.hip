@@ -1,0 +1,144 @@
+// Planner: for every (tile column, trace) of a frame, the range of samples
+// whose PSF footprint can reach the column, the tile rows they can reach and
+// the PSF node cells they fall in.  x grows strictly along a trace (checked
+// at format load), so each range is found by bisection on the same FP64
+// positions the render kernels evaluate.
+#include "dev_common.h"
+
+namespace e2e {
+
+namespace {
+
+__device__ double x_at(const TraceDev &T, double t0, double dt, int k)
+{
+    double t = fma((double)k, dt, t0);
+    double v = T.cx[T.degx];
+    for (int j = T.degx - 1; j >= 0; --j) v = fma(v, t, T.cx[j]);
+    return v;
+}
+
+__device__ double y_at_t(const TraceDev &T, double t)
+{
+    double v = T.cy[T.degy];
+    for (int j = T.degy - 1; j >= 0; --j) v = fma(v, t, T.cy[j]);
+    return v;
+}
+
+// first k in [lo, hi] with x(k) >= xv (hi if none)
+__device__ int first_at_or_above(const TraceDev &T, double t0, double dt, double xv, int lo,
+                                 int hi)
+{
+    while (lo < hi) {
+        int mid = lo + (hi - lo) / 2;
+        if (x_at(T, t0, dt, mid) >= xv) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+__device__ int cell_of(double p, double gs, int g)
+{
+    double f;
+    return node_cell(p, gs, g, &f);
+}
+
+__global__ void k_plan(const FrameDev *__restrict__ frames, int *__restrict__ err)
+{
+    const FrameDev &F = frames[blockIdx.y];
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= F.ntx * F.ntr) return;
+    int c = idx / F.ntr, tr = idx % F.ntr;
+    const TraceDev &T = F.tr[tr];
+    SegDev S;
+    S.k0 = 0; S.k1 = 0; S.ty0 = 1; S.ty1 = 0;
+    S.cx0 = S.cx1 = S.cy0 = S.cy1 = 0;
+
+    double t0, dt;
+    trace_affine(T, F.beta, &t0, &dt);
+    int X0 = c * F.tw, X1 = min(X0 + F.tw, F.nx);
+    const bool table = F.psf_kind == E2E_PSF_TABLE;
+    double hw = table ? (double)F.kw / (2.0 * kOS) : 0.0;
+    double xlo, xhi;
+    if (table) {
+        xlo = X0 - 0.5 - hw;
+        xhi = X1 - 0.5 + hw;
+    } else {
+        xlo = X0 - F.H - 0.5;
+        xhi = X1 + F.H - 0.5;
+    }
+    xlo -= 1e-3;
+    xhi += 1e-3;
+    int k0 = first_at_or_above(T, t0, dt, xlo, 0, T.n);
+    int k1 = first_at_or_above(T, t0, dt, xhi, k0, T.n);
+    if (k0 < k1) {
+        // y range over [k0, k1): 9 nodes plus the curvature bound between them
+        const int NP = 9;
+        double ta = fma((double)k0, dt, t0), tb = fma((double)(k1 - 1), dt, t0);
+        double ymin = 1e300, ymax = -1e300;
+        for (int q = 0; q < NP; ++q) {
+            double t = (q == NP - 1) ? tb : ta + (tb - ta) * (double)q / (NP - 1);
+            double y = y_at_t(T, t);
+            ymin = fmin(ymin, y);
+            ymax = fmax(ymax, y);
+        }
+        double h = fabs(tb - ta) / (NP - 1);
+        double m = T.y2max * h * h / 8.0 + 1e-6;
+        ymin -= m;
+        ymax += m;
+        int jlo, jhi;
+        if (table) {
+            jlo = (int)floor(ymin - hw - 0.5) - 1;
+            jhi = (int)ceil(ymax + hw + 0.5) + 1;
+        } else {
+            jlo = (int)floor(ymin + 0.5) - F.H - 1;
+            jhi = (int)floor(ymax + 0.5) + F.H + 1;
+        }
+        int ty0 = max(floordiv(jlo, F.th), 0);
+        int ty1 = min(floordiv(jhi, F.th), F.nty - 1);
+        if (ty0 <= ty1) {
+            S.k0 = k0;
+            S.k1 = k1;
+            S.ty0 = (int16_t)ty0;
+            S.ty1 = (int16_t)ty1;
+            if (table) {
+                int ca = cell_of(x_at(T, t0, dt, k0), F.gsx, F.gx);
+                int cb = cell_of(x_at(T, t0, dt, k1 - 1), F.gsx, F.gx);
+                int ra = cell_of(ymin, F.gsy, F.gy);
+                int rb = cell_of(ymax, F.gsy, F.gy);
+                if (cb - ca > 1 || rb - ra > 1) atomicOr(err, kErrCells);
+                S.cx0 = (int8_t)ca;
+                S.cx1 = (int8_t)min(cb, ca + 1);
+                S.cy0 = (int8_t)ra;
+                S.cy1 = (int8_t)min(rb, ra + 1);
+            }
+        }
+    }
+    F.segs[(size_t)c * F.ntr + tr] = S;
+}
+
+__global__ void k_fill_i32(int *p, int n, int v)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_plan(const FrameDev *frames_dev, const FrameDev *frames_host, int n_frames,
+                       int *err, hipStream_t s)
+{
+    int maxw = 0;
+    for (int f = 0; f < n_frames; ++f) maxw = max(maxw, frames_host[f].ntx * frames_host[f].ntr);
+    if (maxw == 0) return hipSuccess;
+    dim3 grid((maxw + 255) / 256, n_frames);
+    hipLaunchKernelGGL(k_plan, grid, dim3(256), 0, s, frames_dev, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int *p, int n, int v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace e2e

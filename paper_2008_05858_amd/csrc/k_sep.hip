@@ -1,0 +1,235 @@
+// Render path for analytic Gaussian PSFs (Sec. 2.1: Gaussian aberration
+// model), circular (GAUSS_ERF) or axis-aligned with (sigma_x, sigma_y)
+// interpolated across the field (SEPARABLE).  A pixel's weight is the exact
+// integral of the Gaussian over the pixel (Sec. 2.2: SFI integrated over the
+// pixel area), i.e. a product of normal-CDF differences per axis, over a
+// (2H+1)^2 window around floor(x + 1/2), renormalised by the window sum.
+//
+// Positions are FP64; the CDF differences are evaluated in FP32 on
+// pixel-relative offsets (|offset| <= H + 1), each edge through one erfc on
+// the side of the distribution where nothing cancels.  One workgroup owns a
+// 16 x 16 tile, stages 256 samples' per-axis weights in LDS and lets each
+// thread gather its pixel's contributions in sample order (FP64 or FP32
+// sums), so the result is deterministic and written once.
+#include "dev_common.h"
+
+namespace e2e {
+
+namespace {
+
+constexpr int kMaxH = 8;
+constexpr int kChunk = 256;
+
+// Per-axis weights of a Gaussian centred at pixel offset d in [-1/2, 1/2)
+// from anchor pixel 0: w[m] = (Phi(e_{m+1}) - Phi(e_m)) / norm for pixels
+// m - H, with e_m = (m - H - 1/2 - d) / sg.  Each edge uses one erfc of its
+// absolute value: c_m = Phi(-|e_m|).
+__device__ void axis_weights(float d, float sg, int H, float scale, float *w)
+{
+    const float r = 0.70710678118654752f;
+    float inv = 1.0f / sg;
+    float cprev = 0.f;
+    bool pprev = false;
+    float c0 = 0.f, clast = 0.f;
+    for (int m = 0; m <= 2 * H + 1; ++m) {
+        float e = ((float)(m - H) - 0.5f - d) * inv;
+        float c = 0.5f * erfcf(fabsf(e) * r);
+        bool pos = e >= 0.0f;
+        if (m > 0) {
+            float v;
+            if (pprev) v = cprev - c;            // both edges right of the centre
+            else if (!pos) v = c - cprev;        // both left
+            else v = (1.0f - cprev) - c;         // straddles the centre
+            w[m - 1] = v;
+        } else {
+            c0 = c;
+        }
+        cprev = c;
+        pprev = pos;
+        clast = c;
+    }
+    float norm = (1.0f - c0) - clast;
+    float f = scale / norm;
+    for (int m = 0; m <= 2 * H; ++m) w[m] *= f;
+}
+
+template <int DX, int DY, typename ST, bool SEP, bool ACC64>
+__global__ __launch_bounds__(256) void k_render_sep(const FrameDev *__restrict__ frames,
+                                                    const int2 *__restrict__ work, int n_work,
+                                                    int *__restrict__ counter,
+                                                    int *__restrict__ err)
+{
+    constexpr int TS = kSepTile;
+    constexpr int WMAX = 2 * kMaxH + 1;
+    __shared__ int sax[kChunk], say[kChunk];
+    __shared__ float swx[kChunk][WMAX + 1], swy[kChunk][WMAX + 1];
+    __shared__ int tlist[kMaxTileTraces];
+    __shared__ int sh_count, sh_item;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    for (int iter = 0;; ++iter) {
+        int fi, tile_id;
+        if (work == nullptr) {
+            if (iter > 0) break;
+            fi = 0;
+            tile_id = xcd_remap(blockIdx.x, gridDim.x);
+        } else {
+            if (tid == 0) sh_item = atomicAdd(counter, 1);
+            __syncthreads();
+            int w = uniform_i(sh_item);
+            if (w >= n_work) break;
+            int2 wk = work[w];
+            fi = uniform_i(wk.x);
+            tile_id = uniform_i(wk.y);
+        }
+        const FrameDev &F = frames[fi];
+        const int ntr = F.ntr, H = F.H;
+        const int tx = tile_id % F.ntx, ty = tile_id / F.ntx;
+        const int X0 = tx * TS, Y0 = ty * TS;
+        const SegDev *segs = F.segs + (size_t)tx * ntr;
+        if (tid < 64) {
+            int cnt = 0;
+            for (int base = 0; base < ntr; base += 64) {
+                int tr = base + lane;
+                bool ok = false;
+                if (tr < ntr) {
+                    SegDev s = segs[tr];
+                    ok = s.k0 < s.k1 && s.ty0 <= ty && ty <= s.ty1;
+                }
+                unsigned long long m = __ballot(ok);
+                int pos = cnt + __popcll(m & ((1ull << lane) - 1ull));
+                if (ok) {
+                    if (pos < kMaxTileTraces) tlist[pos] = tr;
+                    else atomicOr(err, kErrTileTraces);
+                }
+                cnt += __popcll(m);
+            }
+            if (lane == 0) sh_count = min(cnt, kMaxTileTraces);
+        }
+        __syncthreads();
+        const int count = uniform_i(sh_count);
+        const int pi = X0 + (tid % TS), pj = Y0 + (tid / TS);
+        double acc64 = 0.0;
+        float acc32 = 0.0f;
+
+        for (int li = 0; li < count; ++li) {
+            const int tr = uniform_i(tlist[li]);
+            const TraceDev &T = F.tr[tr];
+            const SegDev sg = segs[tr];
+            double cxr[DX + 1], cyr[DY + 1];
+#pragma unroll
+            for (int j = 0; j <= DX; ++j) cxr[j] = T.cx[j];
+#pragma unroll
+            for (int j = 0; j <= DY; ++j) cyr[j] = T.cy[j];
+            double t0, dt;
+            trace_affine(T, F.beta, &t0, &dt);
+            const float scale = (float)(T.thr * F.flux_scale);
+            const ST *spec = (const ST *)F.spec[T.slot];
+            for (int kc = sg.k0; kc < sg.k1; kc += kChunk) {
+                const int nk = min(kChunk, sg.k1 - kc);
+                if (tid < nk) {
+                    const int k = kc + tid;
+                    double t = fma((double)k, dt, t0);
+                    double x = horner<DX>(cxr, t);
+                    double y = horner<DY>(cyr, t);
+                    double axd = floor(x + 0.5), ayd = floor(y + 0.5);
+                    float sgx, sgy;
+                    if (SEP) {
+                        double fx, fy;
+                        int cx = node_cell(x, F.gsx, F.gx, &fx);
+                        int cy = node_cell(y, F.gsy, F.gy, &fy);
+                        int cx1 = min(cx + 1, F.gx - 1), cy1 = min(cy + 1, F.gy - 1);
+                        const float *s = F.sxy;
+                        auto S = [&](int l, int m, int c) {
+                            return (double)s[((size_t)l * F.gx + m) * 2 + c];
+                        };
+                        double gx0 = 1.0 - fx, gy0 = 1.0 - fy;
+                        sgx = (float)(gx0 * gy0 * S(cy, cx, 0) + fx * gy0 * S(cy, cx1, 0) +
+                                      gx0 * fy * S(cy1, cx, 0) + fx * fy * S(cy1, cx1, 0));
+                        sgy = (float)(gx0 * gy0 * S(cy, cx, 1) + fx * gy0 * S(cy, cx1, 1) +
+                                      gx0 * fy * S(cy1, cx, 1) + fx * fy * S(cy1, cx1, 1));
+                    } else {
+                        sgx = sgy = (float)F.sigma;
+                    }
+                    float phi = (float)spec_at(spec, k) * scale;
+                    axis_weights((float)(x - axd), sgx, H, phi, swx[tid]);
+                    axis_weights((float)(y - ayd), sgy, H, 1.0f, swy[tid]);
+                    sax[tid] = (int)axd - H;
+                    say[tid] = (int)ayd - H;
+                }
+                __syncthreads();
+                const int W = 2 * H;
+                for (int s = 0; s < nk; ++s) {
+                    int dx = pi - sax[s], dy = pj - say[s];
+                    if ((unsigned)dx <= (unsigned)W && (unsigned)dy <= (unsigned)W) {
+                        float v = swx[s][dx] * swy[s][dy];
+                        if (ACC64) acc64 += (double)v;
+                        else acc32 += v;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (pi < F.nx && pj < F.ny) {
+            double v = ACC64 ? acc64 : (double)acc32;
+            size_t o = (size_t)pj * F.nx + pi;
+            if (F.out_f64) ((double *)F.out)[o] = v;
+            else ((float *)F.out)[o] = (float)v;
+        }
+        __syncthreads();
+    }
+}
+
+template <int DX, int DY, typename ST>
+hipError_t launch_st(const FrameDev *frames_dev, const KernelCfg &cfg, bool sep,
+                     const int2 *work, int n_work, int *counter, int *err, int nb,
+                     hipStream_t s)
+{
+    bool acc64 = cfg.precision != E2E_PREC_F32;
+    if (sep) {
+        if (acc64)
+            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, true, true>), dim3(nb), dim3(256), 0,
+                               s, frames_dev, work, n_work, counter, err);
+        else
+            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, true, false>), dim3(nb), dim3(256), 0,
+                               s, frames_dev, work, n_work, counter, err);
+    } else {
+        if (acc64)
+            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, false, true>), dim3(nb), dim3(256), 0,
+                               s, frames_dev, work, n_work, counter, err);
+        else
+            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, false, false>), dim3(nb), dim3(256),
+                               0, s, frames_dev, work, n_work, counter, err);
+    }
+    return hipGetLastError();
+}
+
+template <int DX, int DY>
+hipError_t launch_deg(const FrameDev *frames_dev, const KernelCfg &cfg, bool sep,
+                      const int2 *work, int n_work, int *counter, int *err, int nb,
+                      hipStream_t s)
+{
+    if (cfg.spec_f64)
+        return launch_st<DX, DY, double>(frames_dev, cfg, sep, work, n_work, counter, err, nb, s);
+    return launch_st<DX, DY, float>(frames_dev, cfg, sep, work, n_work, counter, err, nb, s);
+}
+
+}  // namespace
+
+// sep is read from the first frame's PSF kind on the host side and passed
+// through cfg.kw: 1 = SEPARABLE, 0 = GAUSS_ERF.
+hipError_t launch_sep(const FrameDev *frames_dev, const KernelCfg &cfg, const int2 *work,
+                      int n_work, int *counter, int *err, hipStream_t s)
+{
+    int nb = work == nullptr ? cfg.plain_tiles : (n_work < 1024 ? n_work : 1024);
+    if (nb <= 0) return hipSuccess;
+    bool sep = cfg.kw != 0;
+    if (cfg.degx <= 3 && cfg.degy <= 2)
+        return launch_deg<3, 2>(frames_dev, cfg, sep, work, n_work, counter, err, nb, s);
+    if (cfg.degx <= 4 && cfg.degy <= 3)
+        return launch_deg<4, 3>(frames_dev, cfg, sep, work, n_work, counter, err, nb, s);
+    return launch_deg<7, 7>(frames_dev, cfg, sep, work, n_work, counter, err, nb, s);
+}
+
+}  // namespace e2e

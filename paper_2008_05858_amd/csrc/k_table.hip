@@ -1,0 +1,385 @@
+// Render path for tabulated, field-dependent PSF maps (Sec. 2.1 maps of
+// cell integrals, interpolated bilinearly across the field).
+//
+// Exact reformulation used here.  With os cells per pixel, a kernel placed at
+// x has its cells on a grid offset by the sub-cell phase rho of
+// u = os x + (os - kw)/2: cell a covers (1 - rho) of slot floor(u) + a and
+// rho of the next slot, and a slot lies wholly inside one pixel.  So the
+// pixel weights of a sample are the CIC split (1 - rho, rho) x (1 - rho_y,
+// rho_y) of four slot-aligned placements, and an aligned placement's pixel
+// weights are box sums of the table over os x os cells (the "taps").  The
+// bilinear field interpolation is linear in the node tables, so a sample's
+// contribution is 16 deposits (2 x-slots x 2 y-rows x 4 nodes) followed by a
+// fixed stencil per node: nothing is approximated.
+//
+// One workgroup owns one detector tile (TW x 32 pixels) and writes each of
+// its pixels exactly once; no global atomics.  For every trace reaching the
+// tile (ascending trace order, then node cell) it
+//   1. gives each thread one slot column and finds that column's samples by
+//      a Newton search on the FP64 format polynomial;
+//   2. walks those samples in order (FP64 positions, FP64 register sums of
+//      the 16 deposits, flushed to the column's private 4-row LDS window);
+//   3. per deposit row, densifies the slots and applies the node stencils,
+//      one wave per node, taps read through the scalar cache, FP64 sums in a
+//      rolling register window, then adds the four node partials into the
+//      FP64 LDS tile in node order.
+// The summation order is fixed, so reruns are bitwise identical.
+#include "dev_common.h"
+
+namespace e2e {
+
+namespace {
+
+constexpr int kNone = 0x3fffffff;  // "no row yet"; far from any real row
+
+template <int KW, int DX, int DY, typename ST>
+__global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
+    const FrameDev *__restrict__ frames, const int2 *__restrict__ work, int n_work,
+    int *__restrict__ counter, int *__restrict__ err)
+{
+    constexpr int OS = kOS;
+    constexpr int NCOL = kTableThreads;        // slot columns per tile
+    constexpr int TW = (NCOL - KW) / OS;       // tile width in pixels
+    constexpr int TH = kTableTH;
+    constexpr int NSLOT = NCOL - 1;            // slots that reach the tile
+    constexpr int NS = KW + OS - 1;            // slots per pixel column
+    constexpr int DD = (KW + OS - 2) / OS + 1; // pixel rows per deposit row
+    constexpr int NODE = OS * NS * DD;         // taps per node
+    constexpr double UC = 0.5 * (OS - KW);
+    static_assert(OS * TW + KW == NCOL, "tile geometry");
+    static_assert(TW <= 64, "one wave spans the tile width");
+
+    __shared__ float W[4][2][4][NCOL];          // per-column deposit windows
+    __shared__ int rbase[NCOL];                 // window base row per column
+    __shared__ float D[4][OS][OS][64];          // one deposit row, phase split
+    __shared__ double tile[TH][TW];
+    __shared__ double P[2][4][64];
+    __shared__ int kst[NCOL + 1];
+    __shared__ int tlist[kMaxTileTraces];
+    __shared__ int flags[2][4][OS];
+    __shared__ int sh_count, sh_item, sh_qmin, sh_qmax;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+    for (int iter = 0;; ++iter) {
+        int fi, tile_id;
+        if (work == nullptr) {
+            if (iter > 0) break;
+            fi = 0;
+            tile_id = xcd_remap(blockIdx.x, gridDim.x);
+        } else {
+            if (tid == 0) sh_item = atomicAdd(counter, 1);
+            __syncthreads();
+            int w = uniform_i(sh_item);
+            if (w >= n_work) break;
+            int2 wk = work[w];
+            fi = uniform_i(wk.x);
+            tile_id = uniform_i(wk.y);
+        }
+        cptr<FrameDev> Fp = as_const(frames) + fi;
+        const int ntr = Fp->ntr;
+        const int tx = tile_id % Fp->ntx, ty = tile_id / Fp->ntx;
+        const int X0 = tx * TW, Y0 = ty * TH;
+        const SegDev *segs = Fp->segs + (size_t)tx * ntr;
+        const double beta = Fp->beta, flux_scale = Fp->flux_scale, gsx = Fp->gsx, gsy = Fp->gsy;
+        const int gxn = Fp->gx, gyn = Fp->gy;
+
+        // ---- traces reaching this tile, ascending
+        if (tid < 64) {
+            int cnt = 0;
+            for (int base = 0; base < ntr; base += 64) {
+                int tr = base + lane;
+                bool ok = false;
+                if (tr < ntr) {
+                    SegDev s = segs[tr];
+                    ok = s.k0 < s.k1 && s.ty0 <= ty && ty <= s.ty1;
+                }
+                unsigned long long m = __ballot(ok);
+                int pos = cnt + __popcll(m & ((1ull << lane) - 1ull));
+                if (ok) {
+                    if (pos < kMaxTileTraces) tlist[pos] = tr;
+                    else atomicOr(err, kErrTileTraces);
+                }
+                cnt += __popcll(m);
+            }
+            if (lane == 0) sh_count = min(cnt, kMaxTileTraces);
+        }
+        for (int e = tid; e < TH * TW; e += kTableThreads) tile[e / TW][e % TW] = 0.0;
+        __syncthreads();
+        const int count = uniform_i(sh_count);
+
+        for (int li = 0; li < count; ++li) {
+            const int tr = uniform_i(tlist[li]);
+            cptr<TraceDev> Tp = as_const(Fp->tr) + tr;
+            const SegDev sg = segs[tr];
+            double cxr[DX + 1], cyr[DY + 1];
+#pragma unroll
+            for (int j = 0; j <= DX; ++j) cxr[j] = Tp->cx[j];
+#pragma unroll
+            for (int j = 0; j <= DY; ++j) cyr[j] = Tp->cy[j];
+            TraceDev Tl;
+            Tl.lmin = Tp->lmin;
+            Tl.lmax = Tp->lmax;
+            Tl.n = Tp->n;
+            double t0, dt;
+            trace_affine(Tl, beta, &t0, &dt);
+            const double scale = Tp->thr * flux_scale;
+            gptr<ST> spec = as_global((const ST *)as_const(Fp->spec)[Tp->slot]);
+            const int k0 = sg.k0, k1 = sg.k1;
+            double ua = fma(horner<DX>(cxr, fma((double)k0, dt, t0)), (double)OS, UC);
+            double ub = fma(horner<DX>(cxr, fma((double)(k1 - 1), dt, t0)), (double)OS, UC);
+
+            for (int cyc = sg.cy0; cyc <= sg.cy1; ++cyc)
+            for (int cxc = sg.cx0; cxc <= sg.cx1; ++cxc) {
+                // ---- 1. samples of each slot column: first k with u(k) >= q
+                const int q = OS * X0 - KW + tid;
+                auto u_of = [&](int k) {
+                    double x = horner<DX>(cxr, fma((double)k, dt, t0));
+                    return fma(x, (double)OS, UC);
+                };
+                auto search = [&](int qq) -> int {
+                    if ((double)qq <= ua) return k0;
+                    if ((double)qq > ub) return k1;
+                    double kk = (double)k0 + ((double)qq - ua) / (ub - ua) * (double)(k1 - 1 - k0);
+                    for (int it = 0; it < 2; ++it) {
+                        double t = fma(kk, dt, t0), dx;
+                        double x = horner_d<DX>(cxr, t, &dx);
+                        double u = fma(x, (double)OS, UC);
+                        double du = (double)OS * dx * dt;
+                        if (du > 0.0) kk -= (u - (double)qq) / du;
+                        kk = fmin(fmax(kk, (double)k0), (double)(k1 - 1));
+                    }
+                    int k = (int)ceil(kk);
+                    k = min(max(k, k0 + 1), k1 - 1);
+                    int guard = 0;
+                    while (k < k1 && u_of(k) < (double)qq && guard < 256) { ++k; ++guard; }
+                    while (k > k0 && u_of(k - 1) >= (double)qq && guard < 256) { --k; ++guard; }
+                    if (guard >= 256) atomicOr(err, kErrSearch);
+                    return k;
+                };
+                kst[tid] = search(q);
+                if (tid == NCOL - 1) kst[NCOL] = search(q + 1);
+                if (tid == 0) { sh_qmin = 0x7fffffff; sh_qmax = -0x7fffffff; }
+#pragma unroll
+                for (int l = 0; l < 4; ++l)
+#pragma unroll
+                    for (int lr = 0; lr < 2; ++lr)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) W[l][lr][r][tid] = 0.0f;
+                __syncthreads();
+
+                // ---- 2. deposits of this column's samples
+                const int ks = kst[tid], ke = kst[tid + 1];
+                double a[16];
+#pragma unroll
+                for (int e = 0; e < 16; ++e) a[e] = 0.0;
+                int runQy = kNone, rb = kNone;
+                int qmin = 0x7fffffff, qmax = -0x7fffffff;
+                auto flush = [&]() {
+                    int o = runQy - rb;
+                    if (o < 0 || o > 2) {
+                        atomicOr(err, kErrRowWindow);
+                        return;
+                    }
+#pragma unroll
+                    for (int l = 0; l < 4; ++l)
+#pragma unroll
+                        for (int lr = 0; lr < 2; ++lr)
+#pragma unroll
+                            for (int r = 0; r < 2; ++r) {
+                                int e = ((lr * 2 + (l & 1)) * 2 + r) * 2 + (l >> 1);
+                                W[l][lr][o + r][tid] += (float)(a[e] * scale);
+                            }
+                };
+                double sv_next = ks < ke ? spec_at(spec, ks) : 0.0;
+                for (int k = ks; k < ke; ++k) {
+                    double sv = sv_next;
+                    if (k + 1 < ke) sv_next = spec_at(spec, k + 1);
+                    double t = fma((double)k, dt, t0);
+                    double x = horner<DX>(cxr, t);
+                    double y = horner<DY>(cyr, t);
+                    double rx = fma(x, (double)OS, UC) - (double)q;
+                    double vy = fma(y, (double)OS, UC);
+                    double fly = floor(vy);
+                    int Qy = (int)fly;
+                    double ry = vy - fly;
+                    double fx, fy;
+                    int cxs = node_cell(x, gsx, gxn, &fx);
+                    int cys = node_cell(y, gsy, gyn, &fy);
+                    bool in = (cxs == cxc) & (cys == cyc);
+                    double phi = in ? sv : 0.0;
+                    if (Qy != runQy) {
+                        if (runQy != kNone) {
+                            flush();
+#pragma unroll
+                            for (int e = 0; e < 16; ++e) a[e] = 0.0;
+                        }
+                        if (rb == kNone) rb = Qy - 1;
+                        runQy = Qy;
+                    }
+                    if (in) {
+                        qmin = min(qmin, Qy);
+                        qmax = max(qmax, Qy);
+                    }
+                    // x factors [lr][node x], y factors [row][node y]
+                    double p1 = phi * rx, p0 = phi - p1;
+                    double xv[2][2], yv[2][2];
+                    xv[0][1] = p0 * fx; xv[0][0] = p0 - xv[0][1];
+                    xv[1][1] = p1 * fx; xv[1][0] = p1 - xv[1][1];
+                    double e1 = ry, e0 = 1.0 - ry;
+                    yv[0][1] = e0 * fy; yv[0][0] = e0 - yv[0][1];
+                    yv[1][1] = e1 * fy; yv[1][0] = e1 - yv[1][1];
+#pragma unroll
+                    for (int lr = 0; lr < 2; ++lr)
+#pragma unroll
+                        for (int nx = 0; nx < 2; ++nx)
+#pragma unroll
+                            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                                for (int ny = 0; ny < 2; ++ny) {
+                                    int e = ((lr * 2 + nx) * 2 + r) * 2 + ny;
+                                    a[e] = fma(xv[lr][nx], yv[r][ny], a[e]);
+                                }
+                }
+                if (runQy != kNone) flush();
+                rbase[tid] = rb;
+                if (qmin <= qmax) {
+                    atomicMin(&sh_qmin, qmin);
+                    atomicMax(&sh_qmax, qmax);
+                }
+                if (tid < OS * 4 * 2) ((int *)flags)[tid] = 0;
+                __syncthreads();
+
+                // ---- 3. stencils, one deposit row at a time
+                const int qlo = uniform_i(sh_qmin), qhi = uniform_i(sh_qmax) + 1;
+                if (qlo > qhi) continue;  // no sample of this cell here (uniform)
+                const int nlo = floordiv(qlo, OS), nhi = floordiv(qhi, OS);
+                const int nb = max(nlo, Y0 - (DD - 1));
+                const int ne = min(nhi, Y0 + TH - 1);
+                if (nb > ne) continue;
+                const int nlast = min(ne + DD - 1, Y0 + TH - 1);
+                const int mx = min(cxc + (wv & 1), gxn - 1);
+                const int my = min(cyc + (wv >> 1), gyn - 1);
+                cptr<double> taps = as_const(Fp->tb) + (size_t)(my * gxn + mx) * NODE;
+                double acc[DD];
+#pragma unroll
+                for (int d = 0; d < DD; ++d) acc[d] = 0.0;
+                for (int n = nb; n <= nlast; ++n) {
+                    const bool has = n <= ne;
+                    if (has && tid < NSLOT) {
+                        const int sgm = tid;
+                        const int rL = rbase[sgm + 1], rR = rbase[sgm];
+#pragma unroll
+                        for (int p = 0; p < OS; ++p) {
+                            const int r = OS * n + p;
+                            const int oL = r - rL, oR = r - rR;
+                            const bool okL = (unsigned)oL < 4u, okR = (unsigned)oR < 4u;
+#pragma unroll
+                            for (int l = 0; l < 4; ++l) {
+                                float vL = okL ? W[l][0][oL & 3][sgm + 1] : 0.0f;
+                                float vR = okR ? W[l][1][oR & 3][sgm] : 0.0f;
+                                float d = vL + vR;
+                                D[l][p][sgm & 3][sgm >> 2] = d;
+                                if (d != 0.0f) flags[n & 1][l][p] = 1;
+                            }
+                        }
+                    }
+                    if (n > nb && tid < TW) {
+                        int j = n - 1 - Y0;
+                        if (j >= 0)
+                            tile[j][tid] += ((P[(n - 1) & 1][0][tid] + P[(n - 1) & 1][1][tid]) +
+                                             P[(n - 1) & 1][2][tid]) + P[(n - 1) & 1][3][tid];
+                    }
+                    __syncthreads();
+                    if (has) {
+#pragma unroll
+                        for (int p = 0; p < OS; ++p) {
+                            if (uniform_i(flags[n & 1][wv][p]) == 0) continue;
+                            cptr<double> tp = taps + p * NS * DD;
+#pragma unroll 1
+                            for (int s = 0; s < NS; ++s) {
+                                int m = lane + (s >> 2);
+                                double d = (double)D[wv][p][s & 3][m < 64 ? m : 63];
+#pragma unroll
+                                for (int dd = 0; dd < DD; ++dd)
+                                    acc[dd] = fma(d, tp[s * DD + dd], acc[dd]);
+                            }
+                        }
+                    }
+                    if (tid == 0) {
+#pragma unroll
+                        for (int e = 0; e < 4 * OS; ++e) ((int *)flags[(n + 1) & 1])[e] = 0;
+                    }
+                    P[n & 1][wv][lane] = acc[0];
+#pragma unroll
+                    for (int d = 0; d < DD - 1; ++d) acc[d] = acc[d + 1];
+                    acc[DD - 1] = 0.0;
+                    __syncthreads();
+                }
+                if (tid < TW) {
+                    int j = nlast - Y0;
+                    if (j >= 0)
+                        tile[j][tid] += ((P[nlast & 1][0][tid] + P[nlast & 1][1][tid]) +
+                                         P[nlast & 1][2][tid]) + P[nlast & 1][3][tid];
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+
+        // ---- write the tile once
+        for (int e = tid; e < TH * TW; e += kTableThreads) {
+            int r = e / TW, c = e % TW;
+            int gx = X0 + c, gy = Y0 + r;
+            if (gx < Fp->nx && gy < Fp->ny) {
+                size_t o = (size_t)gy * Fp->nx + gx;
+                if (Fp->out_f64) ((double *)Fp->out)[o] = tile[r][c];
+                else ((float *)Fp->out)[o] = (float)tile[r][c];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int KW, int DX, int DY>
+hipError_t launch_kw(const FrameDev *frames_dev, int spec_f64, const int2 *work, int n_work,
+                     int *counter, int *err, int nblocks, hipStream_t s)
+{
+    if (spec_f64)
+        hipLaunchKernelGGL((k_render_table<KW, DX, DY, double>), dim3(nblocks),
+                           dim3(kTableThreads), 0, s, frames_dev, work, n_work, counter, err);
+    else
+        hipLaunchKernelGGL((k_render_table<KW, DX, DY, float>), dim3(nblocks),
+                           dim3(kTableThreads), 0, s, frames_dev, work, n_work, counter, err);
+    return hipGetLastError();
+}
+
+template <int KW>
+hipError_t launch_deg(const FrameDev *frames_dev, int degx, int degy, int spec_f64,
+                      const int2 *work, int n_work, int *counter, int *err, int nblocks,
+                      hipStream_t s)
+{
+    if (degx <= 4 && degy <= 3)
+        return launch_kw<KW, 4, 3>(frames_dev, spec_f64, work, n_work, counter, err, nblocks, s);
+    return launch_kw<KW, 7, 7>(frames_dev, spec_f64, work, n_work, counter, err, nblocks, s);
+}
+
+}  // namespace
+
+hipError_t launch_table(const FrameDev *frames_dev, const KernelCfg &cfg, const int2 *work,
+                        int n_work, int *counter, int *err, hipStream_t s)
+{
+    int nblocks = work == nullptr ? cfg.plain_tiles : (n_work < 512 ? n_work : 512);
+    if (nblocks <= 0) return hipSuccess;
+    if (cfg.kw == 32)
+        return launch_deg<32>(frames_dev, cfg.degx, cfg.degy, cfg.spec_f64, work, n_work,
+                              counter, err, nblocks, s);
+    if (cfg.kw == 48)
+        return launch_deg<48>(frames_dev, cfg.degx, cfg.degy, cfg.spec_f64, work, n_work,
+                              counter, err, nblocks, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace e2e

@@ -1,0 +1,221 @@
+"""ctypes binding of libe2e (include/e2e.h): the same names, marshalling only.
+
+Every step of rendering runs in the library's HIP kernels; this module only
+builds the C structs and converts status codes into exceptions.  It never
+falls back to any other implementation: if ``libe2e.so`` is missing it
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libe2e.so")
+
+E2E_OK, E2E_PENDING = 0, 1
+E2E_EINVAL, E2E_EFORMAT, E2E_EPSF, E2E_ENOMEM, E2E_EAGAIN = -1, -2, -3, -4, -5
+E2E_ENOTFOUND, E2E_EDEVICE, E2E_EBUSY, E2E_EUNSUPPORTED, E2E_EINTERNAL = -6, -7, -8, -9, -10
+E2E_F32, E2E_F64 = 0, 1
+E2E_PSF_GAUSS_ERF, E2E_PSF_TABLE, E2E_PSF_SEPARABLE = 0, 1, 2
+E2E_PREC_F64, E2E_PREC_F32, E2E_PREC_BF16_HILO, E2E_PREC_F16_HILO = 0, 1, 2, 3
+E2E_FLAG_ASYNC = 1
+
+STATUS_NAMES = {0: "E2E_OK", 1: "E2E_PENDING", -1: "E2E_EINVAL", -2: "E2E_EFORMAT",
+                -3: "E2E_EPSF", -4: "E2E_ENOMEM", -5: "E2E_EAGAIN", -6: "E2E_ENOTFOUND",
+                -7: "E2E_EDEVICE", -8: "E2E_EBUSY", -9: "E2E_EUNSUPPORTED",
+                -10: "E2E_EINTERNAL"}
+
+EXPORTS = ["e2e_create", "e2e_destroy", "e2e_last_error", "e2e_version", "e2e_format_load",
+           "e2e_psf_load", "e2e_format_free", "e2e_psf_free", "e2e_render", "e2e_render_batch",
+           "e2e_serve_start", "e2e_serve_submit", "e2e_serve_poll", "e2e_serve_stop",
+           "e2e_noise_poisson", "e2e_philox_blocks", "e2e_set_profiling", "e2e_kernel_time",
+           "e2e_reset_kernel_time"]
+
+
+class e2e_trace_desc(C.Structure):
+    _fields_ = [("order", C.c_int32), ("fiber", C.c_int32), ("slice", C.c_int32),
+                ("lambda_min_nm", C.c_double), ("lambda_max_nm", C.c_double),
+                ("n_samples", C.c_int64), ("deg_x", C.c_int32), ("deg_y", C.c_int32),
+                ("cx", C.POINTER(C.c_double)), ("cy", C.POINTER(C.c_double)),
+                ("throughput", C.c_double), ("spectrum_slot", C.c_int32)]
+
+
+class e2e_psf_desc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("sigma", C.c_double), ("half_width", C.c_int32),
+                ("grid_nx", C.c_int32), ("grid_ny", C.c_int32), ("kw", C.c_int32),
+                ("kh", C.c_int32), ("oversample", C.c_int32),
+                ("tables", C.POINTER(C.c_float)), ("sigma_xy", C.POINTER(C.c_float))]
+
+
+class e2e_render_req(C.Structure):
+    _fields_ = [("fmt", C.c_uint64), ("psf", C.c_uint64), ("spectra", C.POINTER(C.c_void_p)),
+                ("n_spectra", C.c_int32), ("spectrum_dtype", C.c_int32),
+                ("spectra_on_device", C.c_int32), ("rv_mps", C.c_double),
+                ("flux_scale", C.c_double), ("seed", C.c_uint64), ("frame_index", C.c_uint32),
+                ("poisson", C.c_int32), ("precision", C.c_int32), ("out", C.c_void_p),
+                ("out_dtype", C.c_int32), ("out_on_device", C.c_int32),
+                ("hip_stream", C.c_void_p), ("flags", C.c_uint32)]
+
+
+class e2e_render_stats(C.Structure):
+    _fields_ = [("t_submit_us", C.c_double), ("t_admit_us", C.c_double),
+                ("t_launch_us", C.c_double), ("t_done_us", C.c_double),
+                ("footprint_bytes", C.c_uint64), ("status", C.c_int32),
+                ("batch_size", C.c_int32)]
+
+
+class e2e_serve_config(C.Structure):
+    _fields_ = [("max_inflight", C.c_int32), ("max_queue", C.c_int32),
+                ("n_streams", C.c_int32), ("max_batch", C.c_int32)]
+
+
+class E2EError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libe2e.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        L.e2e_create.argtypes = [P(C.c_void_p), C.c_int32, C.c_uint64]
+        L.e2e_destroy.argtypes = [C.c_void_p]
+        L.e2e_destroy.restype = None
+        L.e2e_last_error.restype = C.c_char_p
+        L.e2e_version.restype = C.c_char_p
+        L.e2e_format_load.argtypes = [C.c_void_p, P(e2e_trace_desc), C.c_int32, C.c_int32,
+                                      C.c_int32, P(C.c_uint64)]
+        L.e2e_psf_load.argtypes = [C.c_void_p, P(e2e_psf_desc), P(C.c_uint64)]
+        L.e2e_format_free.argtypes = [C.c_void_p, C.c_uint64]
+        L.e2e_psf_free.argtypes = [C.c_void_p, C.c_uint64]
+        L.e2e_render.argtypes = [C.c_void_p, P(e2e_render_req)]
+        L.e2e_render_batch.argtypes = [C.c_void_p, P(e2e_render_req), C.c_int32]
+        L.e2e_serve_start.argtypes = [C.c_void_p, P(e2e_serve_config)]
+        L.e2e_serve_submit.argtypes = [C.c_void_p, P(e2e_render_req), P(C.c_uint64)]
+        L.e2e_serve_poll.argtypes = [C.c_void_p, C.c_uint64, C.c_int32, P(e2e_render_stats)]
+        L.e2e_serve_stop.argtypes = [C.c_void_p]
+        L.e2e_noise_poisson.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64,
+                                        C.c_uint64, C.c_uint32, C.c_int32, C.c_void_p]
+        L.e2e_philox_blocks.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint64,
+                                        C.c_int64, C.c_uint32, P(C.c_uint32)]
+        L.e2e_set_profiling.argtypes = [C.c_void_p, C.c_int32]
+        L.e2e_kernel_time.argtypes = [C.c_void_p, C.c_char_p, P(C.c_int64), P(C.c_double)]
+        L.e2e_reset_kernel_time.argtypes = [C.c_void_p]
+        for n in EXPORTS:
+            if n not in ("e2e_destroy", "e2e_last_error", "e2e_version"):
+                getattr(L, n).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def check(code):
+    if code < 0:
+        raise E2EError(code, lib().e2e_last_error().decode(errors="replace"))
+    return code
+
+
+# -- same names as the C ABI ------------------------------------------------
+
+def e2e_create(device=0, hbm_budget_bytes=0):
+    h = C.c_void_p()
+    check(lib().e2e_create(C.byref(h), device, hbm_budget_bytes))
+    return h
+
+
+def e2e_destroy(ctx):
+    lib().e2e_destroy(ctx)
+
+
+def e2e_last_error():
+    return lib().e2e_last_error().decode(errors="replace")
+
+
+def e2e_version():
+    return lib().e2e_version().decode()
+
+
+def e2e_format_load(ctx, traces, n_traces, det_nx, det_ny):
+    out = C.c_uint64()
+    check(lib().e2e_format_load(ctx, traces, n_traces, det_nx, det_ny, C.byref(out)))
+    return out.value
+
+
+def e2e_psf_load(ctx, desc):
+    out = C.c_uint64()
+    check(lib().e2e_psf_load(ctx, C.byref(desc), C.byref(out)))
+    return out.value
+
+
+def e2e_format_free(ctx, fid):
+    return check(lib().e2e_format_free(ctx, fid))
+
+
+def e2e_psf_free(ctx, pid):
+    return check(lib().e2e_psf_free(ctx, pid))
+
+
+def e2e_render(ctx, req):
+    return check(lib().e2e_render(ctx, C.byref(req)))
+
+
+def e2e_render_batch(ctx, reqs):
+    arr = (e2e_render_req * len(reqs))(*reqs)
+    return check(lib().e2e_render_batch(ctx, arr, len(reqs)))
+
+
+def e2e_serve_start(ctx, max_inflight=8, max_queue=256, n_streams=2, max_batch=8):
+    cfg = e2e_serve_config(max_inflight, max_queue, n_streams, max_batch)
+    return check(lib().e2e_serve_start(ctx, C.byref(cfg)))
+
+
+def e2e_serve_submit(ctx, req):
+    t = C.c_uint64()
+    check(lib().e2e_serve_submit(ctx, C.byref(req), C.byref(t)))
+    return t.value
+
+
+def e2e_serve_poll(ctx, ticket, timeout_ms=-1):
+    st = e2e_render_stats()
+    code = check(lib().e2e_serve_poll(ctx, ticket, timeout_ms, C.byref(st)))
+    return code, st
+
+
+def e2e_serve_stop(ctx):
+    return check(lib().e2e_serve_stop(ctx))
+
+
+def e2e_noise_poisson(ctx, frame_ptr, dtype, n_pixels, seed, frame_index, on_device,
+                      stream=None):
+    return check(lib().e2e_noise_poisson(ctx, frame_ptr, dtype, n_pixels, seed, frame_index,
+                                         on_device, stream))
+
+
+def e2e_philox_blocks(ctx, seed, frame_index, pixel0, n_pixels, blocks):
+    out = (C.c_uint32 * (4 * n_pixels * blocks))()
+    check(lib().e2e_philox_blocks(ctx, seed, frame_index, pixel0, n_pixels, blocks, out))
+    return out
+
+
+def e2e_set_profiling(ctx, on):
+    return check(lib().e2e_set_profiling(ctx, 1 if on else 0))
+
+
+def e2e_kernel_time(ctx, name):
+    n = C.c_int64()
+    ms = C.c_double()
+    check(lib().e2e_kernel_time(ctx, name.encode(), C.byref(n), C.byref(ms)))
+    return n.value, ms.value
+
+
+def e2e_reset_kernel_time(ctx):
+    return check(lib().e2e_reset_kernel_time(ctx))
