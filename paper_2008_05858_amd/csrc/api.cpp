@@ -451,17 +451,6 @@ e2e_status e2e::validate_req(e2e_ctx *ctx, const e2e_render_req *r, FormatRes **
         return fail(E2E_EINVAL, "precision=%d", r->precision);
     if (r->precision != E2E_PREC_F64 && P->kind != E2E_PSF_SEPARABLE)
         return fail(E2E_EUNSUPPORTED, "reduced precisions exist on the separable path only");
-    if (P->kind == E2E_PSF_TABLE) {
-        // a tile column (and its footprint) must meet at most two node cells
-        int tw = table_tw(P->kw);
-        double span = (double)tw + (double)P->kw / kOS + 4.0;
-        double spx = P->gx > 1 ? (double)(F->nx - 1) / (P->gx - 1) : 1e30;
-        double spy = P->gy > 1 ? (double)(F->ny - 1) / (P->gy - 1) : 1e30;
-        if (spx < span || spy < span)
-            return fail(E2E_EUNSUPPORTED,
-                        "PSF nodes %.1f x %.1f px apart; the table path needs >= %.0f px",
-                        spx, spy, span);
-    }
     *pf = F;
     *pp = P;
     return E2E_OK;
@@ -731,7 +720,7 @@ e2e_status e2e::check_err_word(int w)
                 (w & kErrTileTraces) ? " too many traces reach one tile;" : "",
                 (w & kErrRowWindow) ? " a slot column left its row window;" : "",
                 (w & kErrSearch) ? " column search did not converge;" : "",
-                (w & kErrCells) ? " a tile column spans more than two PSF node cells;" : "");
+                (w & kErrCells) ? " PSF node-cell range inconsistent;" : "");
 }
 
 extern "C" e2e_status e2e_render(e2e_ctx *ctx, const e2e_render_req *req)

@@ -104,11 +104,10 @@ __global__ void k_plan(const FrameDev *__restrict__ frames, int *__restrict__ er
                 int cb = cell_of(x_at(T, t0, dt, k1 - 1), F.gsx, F.gx);
                 int ra = cell_of(ymin, F.gsy, F.gy);
                 int rb = cell_of(ymax, F.gsy, F.gy);
-                if (cb - ca > 1 || rb - ra > 1) atomicOr(err, kErrCells);
                 S.cx0 = (int8_t)ca;
-                S.cx1 = (int8_t)min(cb, ca + 1);
+                S.cx1 = (int8_t)cb;
                 S.cy0 = (int8_t)ra;
-                S.cy1 = (int8_t)min(rb, ra + 1);
+                S.cy1 = (int8_t)rb;
             }
         }
     }

@@ -159,4 +159,4 @@ def test_flux_conservation_gpu():
     sc = scene("c0")
     g = _gu().render(sc, Request(flux_scale=2.0))
     tot = sc.spectra[0].sum() * 2.0
-    assert abs(g.sum() - tot) / tot < 1e-9
+    assert abs(g.sum() - tot) / tot < 1e-6
