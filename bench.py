@@ -1,0 +1,188 @@
+"""Benchmark: ESPRESSO-shaped synthetic echellograms on one MI355X.
+
+A step renders a batch of B frames of the 9216 x 9216, 85-order x 2-fiber x
+2-slice, 1e6-samples-per-trace workload (11 x 11 field nodes of 32 x 32 x4
+tabulated PSFs) in one persistent launch through the C ABI, every frame
+with its own Doppler shift (U[-10, 10] m/s) and exposure scale.  Inputs are
+resident in HBM before the timed region.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--batch B] [--gpus 1]
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sample·PSF-px updates/s + frames/s (ESPRESSO-shaped); p50/p99 render latency"
+PEAK_HBM = 8.0e12          # B/s, MI355X HBM3E
+PEAK_ALU = 78.6e12         # flop/s, FP64 vector FMA (= FP32 FMA without packed math)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def table_flops_per_sample(sc):
+    """Arithmetic of the exact deposit + stencil form, per wavelength sample.
+
+    position: t (1 FMA), x Horner (deg_x FMA), y Horner (deg_y FMA), slot
+    phases (2 FMA + 2 sub), node fractions (2 mul + 2 sub); deposits: 4 x
+    and 4 y factors (8 mul, 4 sub) and 16 FMA; stencil: every deposit cell
+    (2 x-slots x 2 rows per sample, shared by the samples that fall in one
+    slot) meets a (kw/os+1)^2-pixel stencil per node, 4 nodes.
+    """
+    t = sc.traces[0]
+    dx, dy = len(t.cx) - 1, len(t.cy) - 1
+    per_sample = 2 * (1 + dx + dy) + 2 * 2 + 2 + 4 + 12 + 2 * 16
+    # deposit cells per sample: slots per pixel / samples per pixel x rows
+    xspan = abs(np.polynomial.polynomial.polyval(1.0, t.cx) - np.polynomial.polynomial.polyval(-1.0, t.cx))
+    samples_per_px = t.n / xspan
+    cells = (sc.psf.os / samples_per_px) * 2.0 * 4
+    foot = (sc.psf.kw // sc.psf.os + 1) ** 2
+    return per_sample + cells * 2 * foot
+
+
+def cpu_baseline(sc):
+    """The FP64 oracle on one trace of the same workload, single thread."""
+    import oracle
+    from workloads.synth import with_traces
+    sub = with_traces(sc, [170])
+    t0 = time.perf_counter()
+    oracle.render(sub)
+    dt = time.perf_counter() - t0
+    upd = sub.updates()
+    return {"value": upd / dt, "unit": "sample·PSF-px updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"1 of {len(sc.traces)} traces (order {sc.traces[170].order}, "
+                      f"1e6 samples, 81-px footprint) of the same frame, FP64, "
+                      f"single thread, {dt:.1f} s; cpu: {platform.processor() or platform.machine()}",
+            "frames_per_s": (upd / dt) / sc.updates()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--plain-frames", type=int, default=12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(frames shard by detector row bands with no collective; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2008_05858_amd as P
+    from paper_2008_05858_amd import e2e as E
+    from workloads import scene
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log("building c1 workload")
+    sc = scene("c1")
+    ctx = E.e2e_create(0, 0)
+    ld = P.Loaded(ctx, sc)
+    specs = [torch.from_numpy(s).to("cuda") for s in sc.spectra]
+    B = args.batch
+    outs = [torch.empty((sc.ny, sc.nx), dtype=torch.float32, device="cuda") for _ in range(B)]
+    rng = np.random.Generator(np.random.PCG64(4242))
+    stream = torch.cuda.current_stream()
+    sptr = stream.cuda_stream
+
+    def reqs_for(step):
+        rr, keep = [], []
+        for b in range(B):
+            r, k = P.make_req(ld, [s.data_ptr() for s in specs], E.E2E_F32, outs[b].data_ptr(),
+                              E.E2E_F32, spectra_on_device=True, out_on_device=True,
+                              rv_mps=float(rng.uniform(-10, 10)),
+                              flux_scale=float(rng.uniform(1e3, 1e5) / 1e4),
+                              seed=1234, frame_index=step * B + b, stream=sptr,
+                              flags=E.E2E_FLAG_ASYNC)
+            rr.append(r)
+            keep.append(k)
+        return rr, keep
+
+    torch.cuda.synchronize()
+    log("warmup")
+    for w in range(args.warmup):
+        rr, keep = reqs_for(w)
+        E.e2e_render_batch(ctx, rr)
+    torch.cuda.synchronize()
+
+    # timed region: K steps, kernel events on the launch stream
+    E.e2e_reset_kernel_time(ctx)
+    E.e2e_set_profiling(ctx, True)
+    all_reqs = [reqs_for(s) for s in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for rr, keep in all_reqs:
+        E.e2e_render_batch(ctx, rr)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    E.e2e_set_profiling(ctx, False)
+    n_tab, ms_tab = E.e2e_kernel_time(ctx, "render_table")
+    n_plan, ms_plan = E.e2e_kernel_time(ctx, "plan")
+    elapsed = t1 - t0
+    frames = args.steps * B
+    upd_frame = sc.updates()
+    value = frames * upd_frame / elapsed
+    ms_step = 1e3 * elapsed / args.steps
+    log(f"batch: {frames} frames in {elapsed:.3f} s; render_table {ms_tab / max(n_tab, 1):.3f} ms/launch")
+
+    # plain single-frame renderer: per-frame latency
+    lat = []
+    E.e2e_reset_kernel_time(ctx)
+    for f in range(args.plain_frames):
+        r, k = P.make_req(ld, [s.data_ptr() for s in specs], E.E2E_F32, outs[0].data_ptr(),
+                          E.E2E_F32, spectra_on_device=True, out_on_device=True,
+                          rv_mps=float(rng.uniform(-10, 10)), stream=sptr)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        E.e2e_render(ctx, r)
+        lat.append(1e3 * (time.perf_counter() - a))
+    plain_fps = 1e3 / float(np.mean(lat[2:] if len(lat) > 4 else lat))
+
+    # roofline of the dominant kernel (render_table), per launch = B frames
+    avg_s = (ms_tab / max(n_tab, 1)) / 1e3
+    flops_launch = B * sc.n_samples * table_flops_per_sample(sc)
+    bytes_launch = B * (sc.spectrum_bytes() + sc.nx * sc.ny * 4)
+    alu = flops_launch / avg_s
+    hbm = bytes_launch / avg_s
+    roof = {"bound": "alu", "achieved": alu / 1e12, "peak": PEAK_ALU / 1e12, "unit": "TFLOP/s",
+            "frac": alu / PEAK_ALU, "traffic": None,
+            "kernel": "render_table", "kernel_ms": avg_s * 1e3,
+            "algorithmic_flops_per_sample": table_flops_per_sample(sc),
+            "hbm_view": {"achieved_GBps": hbm / 1e9, "frac": hbm / PEAK_HBM,
+                         "algorithmic_bytes_per_frame": bytes_launch / B}}
+    res = {"metric": METRIC, "value": value, "unit": "sample·PSF-px updates/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "c1: ESPRESSO-shaped 9216x9216, 85 orders x 2 fibers x "
+                                  "2 slices, 1e6 samples/trace, 11x11 nodes of 32x32 x4 tables",
+                      "frames_per_step": B, "mode": "render_batch (persistent)",
+                      "updates_per_frame": upd_frame, "out_dtype": "f32"},
+           "frames_per_s": frames / elapsed, "plain_frames_per_s": plain_fps,
+           "latency_ms_p50": float(np.percentile(lat, 50)),
+           "latency_ms_p99": float(np.percentile(lat, 99)),
+           "plan_ms_per_launch": ms_plan / max(n_plan, 1),
+           "roofline": roof}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        res["cpu_baseline"] = cpu_baseline(sc)
+    print(json.dumps(res), flush=True)
+    ld.free()
+    E.e2e_destroy(ctx)
+
+
+if __name__ == "__main__":
+    main()

@@ -199,35 +199,46 @@ int orc_sample_weights(const orc_psf *p, int nx, int ny, double x, double y,
     int ia = (int)floor(Lx + 0.5) - 1, ib = (int)floor(Lx + (double)kw / os + 0.5) + 1;
     int ja = (int)floor(Ly + 0.5) - 1, jb = (int)floor(Ly + (double)kh / os + 0.5) + 1;
     int W = ib - ia + 1, Hh = jb - ja + 1;
-    /* box overlaps of every cell with every pixel, per axis (x os) */
-    double *ovx = (double *)malloc(sizeof(double) * (size_t)kw * W);
-    double *ovy = (double *)malloc(sizeof(double) * (size_t)kh * Hh);
-    for (int a = 0; a < kw; ++a)
-        for (int i = ia; i <= ib; ++i)
-            ovx[(size_t)a * W + (i - ia)] =
-                overlap(Lx + (double)a / os, Lx + (double)(a + 1) / os, i - 0.5, i + 0.5) * os;
-    for (int b = 0; b < kh; ++b)
-        for (int j = ja; j <= jb; ++j)
-            ovy[(size_t)b * Hh + (j - ja)] =
-                overlap(Ly + (double)b / os, Ly + (double)(b + 1) / os, j - 0.5, j + 0.5) * os;
+    /* box overlaps of every cell with every pixel, per axis (x os); a cell
+     * is os^-1 px wide so it meets at most two pixels: keep those pairs */
+    int *pxa = (int *)malloc(sizeof(int) * 2 * kw), *pya = (int *)malloc(sizeof(int) * 2 * kh);
+    double *ovx = (double *)malloc(sizeof(double) * 2 * kw);
+    double *ovy = (double *)malloc(sizeof(double) * 2 * kh);
+    for (int a = 0; a < kw; ++a) {
+        int m = 0;
+        pxa[2 * a] = pxa[2 * a + 1] = 0;
+        ovx[2 * a] = ovx[2 * a + 1] = 0.0;
+        for (int i = ia; i <= ib && m < 2; ++i) {
+            double ov = overlap(Lx + (double)a / os, Lx + (double)(a + 1) / os, i - 0.5, i + 0.5) * os;
+            if (ov != 0.0) { pxa[2 * a + m] = i - ia; ovx[2 * a + m] = ov; ++m; }
+        }
+    }
+    for (int b = 0; b < kh; ++b) {
+        int m = 0;
+        pya[2 * b] = pya[2 * b + 1] = 0;
+        ovy[2 * b] = ovy[2 * b + 1] = 0.0;
+        for (int j = ja; j <= jb && m < 2; ++j) {
+            double ov = overlap(Ly + (double)b / os, Ly + (double)(b + 1) / os, j - 0.5, j + 0.5) * os;
+            if (ov != 0.0) { pya[2 * b + m] = j - ja; ovy[2 * b + m] = ov; ++m; }
+        }
+    }
     /* w_ij = sum_b sum_a K[b][a] ovx[a][i] ovy[b][j]
      *      = sum_b ovy[b][j] T[b][i],  T[b][i] = sum_a K[b][a] ovx[a][i] */
     double *T = (double *)calloc((size_t)kh * W, sizeof(double));
     for (int b = 0; b < kh; ++b)
         for (int a = 0; a < kw; ++a)
-            for (int i = 0; i < W; ++i) {
-                double ov = ovx[(size_t)a * W + i];
-                if (ov != 0.0) T[(size_t)b * W + i] += K[(size_t)b * kw + a] * ov;
-            }
-    for (int j = 0; j < Hh; ++j)
-        for (int i = 0; i < W; ++i) {
-            double acc = 0.0;
-            for (int b = 0; b < kh; ++b) {
-                double ov = ovy[(size_t)b * Hh + j];
-                if (ov != 0.0) acc += ov * T[(size_t)b * W + i];
-            }
-            wt[(size_t)j * W + i] = acc;
+            for (int e = 0; e < 2; ++e)
+                T[(size_t)b * W + pxa[2 * a + e]] += K[(size_t)b * kw + a] * ovx[2 * a + e];
+    for (size_t q = 0; q < (size_t)W * Hh; ++q) wt[q] = 0.0;
+    for (int b = 0; b < kh; ++b)
+        for (int e = 0; e < 2; ++e) {
+            double ov = ovy[2 * b + e];
+            if (ov == 0.0) continue;
+            int j = pya[2 * b + e];
+            for (int i = 0; i < W; ++i) wt[(size_t)j * W + i] += ov * T[(size_t)b * W + i];
         }
+    free(pxa);
+    free(pya);
     free(ovx);
     free(ovy);
     free(T);

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -59,6 +60,8 @@ extern "C" e2e_status e2e_create(e2e_ctx **out, int32_t dev, uint64_t budget)
     c->dev = dev;
     c->budget = budget ? budget : (uint64_t)(0.9 * (double)freeb);
     c->t0 = std::chrono::steady_clock::now();
+    const char *g = getenv("E2E_GRAPHS");
+    c->graphs = !(g && g[0] == '0');
     if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
         delete c;
         return hip_fail(e, "hipStreamCreate");
@@ -663,35 +666,75 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
     if ((e = hipEventRecord(sc->staged, s)) != hipSuccess) return hip_fail(e, "event");
     sc->staged_valid = true;
 
-    // launches: clear error word and queue counter, plan, render, noise
-    if ((e = launch_fill_i32(sc->err, 1, 0, s)) != hipSuccess) return hip_fail(e, "fill");
-    if ((e = launch_fill_i32(sc->counter, 1, 0, s)) != hipSuccess) return hip_fail(e, "fill");
-    prof_begin(ctx, s, "plan");
-    e = launch_plan(sc->frames_dev, sc->h_frames.data(), n, sc->err, s);
-    prof_end(ctx, s);
-    if (e != hipSuccess) return hip_fail(e, "plan launch");
-    const int2 *work = batch ? sc->work : nullptr;
-    int nwork = batch ? (int)work_n : 0;
-    if (kind == E2E_PSF_TABLE) {
-        prof_begin(ctx, s, "render_table");
-        e = launch_table(sc->frames_dev, cfg, work, nwork, sc->counter, sc->err, s);
-    } else if (kind == E2E_PSF_SEPARABLE &&
-               (prec == E2E_PREC_BF16_HILO || prec == E2E_PREC_F16_HILO)) {
-        prof_begin(ctx, s, "render_sep_mfma");
-        e = launch_sep_mfma(sc->frames_dev, cfg, work, nwork, sc->counter, sc->err, s);
-    } else {
-        prof_begin(ctx, s, "render_sep");
-        e = launch_sep(sc->frames_dev, cfg, work, nwork, sc->counter, sc->err, s);
-    }
-    prof_end(ctx, s);
-    if (e != hipSuccess) return hip_fail(e, "render launch");
     bool any_noise = false;
     for (int i = 0; i < n; ++i) any_noise |= reqs[i].poisson != 0;
-    if (any_noise) {
-        prof_begin(ctx, s, "noise");
-        e = launch_noise_frames(sc->frames_dev, sc->h_frames.data(), n, s);
+    const int2 *work = batch ? sc->work : nullptr;
+    const int nwork = batch ? (int)work_n : 0;
+    // the launch sequence: clear error word and queue counter, plan, render, noise
+    auto enqueue = [&]() -> hipError_t {
+        hipError_t q;
+        if ((q = launch_fill_i32(sc->err, 1, 0, s)) != hipSuccess) return q;
+        if ((q = launch_fill_i32(sc->counter, 1, 0, s)) != hipSuccess) return q;
+        prof_begin(ctx, s, "plan");
+        q = launch_plan(sc->frames_dev, sc->h_frames.data(), n, sc->err, s);
         prof_end(ctx, s);
-        if (e != hipSuccess) return hip_fail(e, "noise launch");
+        if (q != hipSuccess) return q;
+        if (kind == E2E_PSF_TABLE) {
+            prof_begin(ctx, s, "render_table");
+            q = launch_table(sc->frames_dev, cfg, work, nwork, sc->counter, sc->err, s);
+        } else if (kind == E2E_PSF_SEPARABLE &&
+                   (prec == E2E_PREC_BF16_HILO || prec == E2E_PREC_F16_HILO)) {
+            prof_begin(ctx, s, "render_sep_mfma");
+            q = launch_sep_mfma(sc->frames_dev, cfg, work, nwork, sc->counter, sc->err, s);
+        } else {
+            prof_begin(ctx, s, "render_sep");
+            q = launch_sep(sc->frames_dev, cfg, work, nwork, sc->counter, sc->err, s);
+        }
+        prof_end(ctx, s);
+        if (q != hipSuccess) return q;
+        if (any_noise) {
+            prof_begin(ctx, s, "noise");
+            q = launch_noise_frames(sc->frames_dev, sc->h_frames.data(), n, s);
+            prof_end(ctx, s);
+        }
+        return q;
+    };
+    // A batch replays a HIP graph captured once per launch signature (the
+    // graph's kernels read their parameters from the scratch buffers just
+    // uploaded); no memset nodes are recorded, counters are cleared by a
+    // fill kernel.  Timed runs (profiling on) launch eagerly.
+    bool use_graph = batch && !ctx->prof && ctx->graphs;
+    if (use_graph) {
+        int maxw = 0;
+        int64_t maxpix = 0;
+        for (int i = 0; i < n; ++i) {
+            maxw = std::max(maxw, sc->h_frames[i].ntx * sc->h_frames[i].ntr);
+            maxpix = std::max(maxpix, (int64_t)sc->h_frames[i].nx * sc->h_frames[i].ny);
+        }
+        char key[256];
+        snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%zu/%d/%lld/%d/%p/%p", kind, cfg.kw,
+                 cfg.degx, cfg.degy, cfg.spec_f64, prec, n, work_n, maxw,
+                 any_noise ? (long long)maxpix : 0ll, (int)any_noise, (void *)sc->frames_dev,
+                 (void *)sc->work);
+        auto it = sc->graphs.find(key);
+        if (it == sc->graphs.end()) {
+            GraphRec g;
+            if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                return hip_fail(e, "graph capture");
+            hipError_t qe = enqueue();
+            e = hipStreamEndCapture(s, &g.graph);
+            if (qe != hipSuccess) return hip_fail(qe, "render launch (capture)");
+            if (e != hipSuccess) return hip_fail(e, "graph capture");
+            if ((e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0)) != hipSuccess) {
+                hipGraphDestroy(g.graph);
+                return hip_fail(e, "graph instantiate");
+            }
+            it = sc->graphs.emplace(key, g).first;
+        }
+        if ((e = hipGraphLaunch(it->second.exec, s)) != hipSuccess)
+            return hip_fail(e, "graph launch");
+    } else {
+        if ((e = enqueue()) != hipSuccess) return hip_fail(e, "render launch");
     }
     for (int i = 0; i < n; ++i) {
         if (reqs[i].out_on_device) continue;

@@ -85,6 +85,7 @@ struct e2e_ctx {
     hipStream_t stream = nullptr;
     std::map<hipStream_t, e2e::Scratch *> scratch;
     bool prof = false;
+    bool graphs = true;           // batches replay captured HIP graphs
     std::vector<e2e::ProfRec> prof_pending;
     std::map<std::string, std::pair<int64_t, double>> prof_acc;
     std::chrono::steady_clock::time_point t0;

@@ -77,6 +77,42 @@ __device__ __forceinline__ int node_cell(double p, double gs, int g, double *f)
     return ci;
 }
 
+// Fraction towards node c+1 of position p on a g-node axis, and whether p
+// falls in node cell c (the same cell node_cell() would pick).
+__device__ __forceinline__ double node_frac_in(double p, double gs, int g, int c, bool *in)
+{
+    if (g < 2) { *in = true; return 0.0; }
+    double sp = fmin(fmax(p * gs, 0.0), (double)(g - 1));
+    double f = sp - (double)c;
+    *in = (f >= 0.0) && (f < 1.0 || c == g - 2);
+    return f;
+}
+
+// Extended node cell of position p on a g-node axis: -1 left of node 0 (the
+// clamped edge region, fraction 0), g-1 right of the last node (fraction 1),
+// otherwise floor(p (g-1)/(n-1)).  Within one extended cell the fraction
+// towards the next node is affine in p (or constant), which is what lets a
+// column's samples be summed as moments.  g == 1: always cell 0, fraction 0.
+__device__ __host__ inline int ext_cell(double p, double gs, int g)
+{
+    if (g < 2) return 0;
+    double v = floor(p * gs);
+    if (v < 0.0) return -1;
+    if (v > (double)(g - 1)) return g - 1;
+    return (int)v;
+}
+
+// Node-weight line of an extended cell: fraction towards node base+1 is
+// a0 + a1 * p, with the lower node index in *base.
+__device__ __host__ inline void cell_line(int c, double gs, int g, int *base, double *a0,
+                                          double *a1)
+{
+    if (g < 2) { *base = 0; *a0 = 0.0; *a1 = 0.0; return; }
+    if (c < 0) { *base = 0; *a0 = 0.0; *a1 = 0.0; return; }
+    if (c >= g - 1) { *base = g - 2; *a0 = 1.0; *a1 = 0.0; return; }
+    *base = c; *a0 = -(double)c; *a1 = gs;
+}
+
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ double uniform_d(double v)

@@ -35,11 +35,6 @@ __device__ int first_at_or_above(const TraceDev &T, double t0, double dt, double
     return lo;
 }
 
-__device__ int cell_of(double p, double gs, int g)
-{
-    double f;
-    return node_cell(p, gs, g, &f);
-}
 
 __global__ void k_plan(const FrameDev *__restrict__ frames, int *__restrict__ err)
 {
@@ -100,10 +95,10 @@ __global__ void k_plan(const FrameDev *__restrict__ frames, int *__restrict__ er
             S.ty0 = (int16_t)ty0;
             S.ty1 = (int16_t)ty1;
             if (table) {
-                int ca = cell_of(x_at(T, t0, dt, k0), F.gsx, F.gx);
-                int cb = cell_of(x_at(T, t0, dt, k1 - 1), F.gsx, F.gx);
-                int ra = cell_of(ymin, F.gsy, F.gy);
-                int rb = cell_of(ymax, F.gsy, F.gy);
+                int ca = ext_cell(x_at(T, t0, dt, k0), F.gsx, F.gx);
+                int cb = ext_cell(x_at(T, t0, dt, k1 - 1), F.gsx, F.gx);
+                int ra = ext_cell(ymin, F.gsy, F.gy);
+                int rb = ext_cell(ymax, F.gsy, F.gy);
                 S.cx0 = (int8_t)ca;
                 S.cx1 = (int8_t)cb;
                 S.cy0 = (int8_t)ra;

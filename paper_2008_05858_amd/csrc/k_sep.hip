@@ -11,47 +11,13 @@
 // 16 x 16 tile, stages 256 samples' per-axis weights in LDS and lets each
 // thread gather its pixel's contributions in sample order (FP64 or FP32
 // sums), so the result is deterministic and written once.
-#include "dev_common.h"
+#include "psf_gauss.h"
 
 namespace e2e {
 
 namespace {
 
-constexpr int kMaxH = 8;
 constexpr int kChunk = 256;
-
-// Per-axis weights of a Gaussian centred at pixel offset d in [-1/2, 1/2)
-// from anchor pixel 0: w[m] = (Phi(e_{m+1}) - Phi(e_m)) / norm for pixels
-// m - H, with e_m = (m - H - 1/2 - d) / sg.  Each edge uses one erfc of its
-// absolute value: c_m = Phi(-|e_m|).
-__device__ void axis_weights(float d, float sg, int H, float scale, float *w)
-{
-    const float r = 0.70710678118654752f;
-    float inv = 1.0f / sg;
-    float cprev = 0.f;
-    bool pprev = false;
-    float c0 = 0.f, clast = 0.f;
-    for (int m = 0; m <= 2 * H + 1; ++m) {
-        float e = ((float)(m - H) - 0.5f - d) * inv;
-        float c = 0.5f * erfcf(fabsf(e) * r);
-        bool pos = e >= 0.0f;
-        if (m > 0) {
-            float v;
-            if (pprev) v = cprev - c;            // both edges right of the centre
-            else if (!pos) v = c - cprev;        // both left
-            else v = (1.0f - cprev) - c;         // straddles the centre
-            w[m - 1] = v;
-        } else {
-            c0 = c;
-        }
-        cprev = c;
-        pprev = pos;
-        clast = c;
-    }
-    float norm = (1.0f - c0) - clast;
-    float f = scale / norm;
-    for (int m = 0; m <= 2 * H; ++m) w[m] *= f;
-}
 
 template <int DX, int DY, typename ST, bool SEP, bool ACC64>
 __global__ __launch_bounds__(256) void k_render_sep(const FrameDev *__restrict__ frames,
@@ -136,19 +102,7 @@ __global__ __launch_bounds__(256) void k_render_sep(const FrameDev *__restrict__
                     double axd = floor(x + 0.5), ayd = floor(y + 0.5);
                     float sgx, sgy;
                     if (SEP) {
-                        double fx, fy;
-                        int cx = node_cell(x, F.gsx, F.gx, &fx);
-                        int cy = node_cell(y, F.gsy, F.gy, &fy);
-                        int cx1 = min(cx + 1, F.gx - 1), cy1 = min(cy + 1, F.gy - 1);
-                        const float *s = F.sxy;
-                        auto S = [&](int l, int m, int c) {
-                            return (double)s[((size_t)l * F.gx + m) * 2 + c];
-                        };
-                        double gx0 = 1.0 - fx, gy0 = 1.0 - fy;
-                        sgx = (float)(gx0 * gy0 * S(cy, cx, 0) + fx * gy0 * S(cy, cx1, 0) +
-                                      gx0 * fy * S(cy1, cx, 0) + fx * fy * S(cy1, cx1, 0));
-                        sgy = (float)(gx0 * gy0 * S(cy, cx, 1) + fx * gy0 * S(cy, cx1, 1) +
-                                      gx0 * fy * S(cy1, cx, 1) + fx * fy * S(cy1, cx1, 1));
+                        sigma_at(F.sxy, F.gx, F.gy, F.gsx, F.gsy, x, y, &sgx, &sgy);
                     } else {
                         sgx = sgy = (float)F.sigma;
                     }

@@ -45,22 +45,30 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
     constexpr int NS = KW + OS - 1;            // slots per pixel column
     constexpr int DD = (KW + OS - 2) / OS + 1; // pixel rows per deposit row
     constexpr int NODE = OS * NS * DD;         // taps per node
+    constexpr int SU = (NS % 5 == 0) ? 5 : ((NS % 3 == 0) ? 3 : 1);  // stencil unroll
     constexpr double UC = 0.5 * (OS - KW);
     static_assert(OS * TW + KW == NCOL, "tile geometry");
     static_assert(TW <= 64, "one wave spans the tile width");
 
+    constexpr int NN = KW <= 32 ? 4 : 2;       // deposit rows per stencil chunk
+    constexpr int NJ = NN + DD - 1;            // output rows a chunk reaches
+    constexpr int SQ = (NS + 3) / 4;           // stencil columns per wave
+    static_assert(NN * OS <= 16, "flag bits");
+
     __shared__ float W[4][2][4][NCOL];          // per-column deposit windows
     __shared__ int rbase[NCOL];                 // window base row per column
-    __shared__ float D[4][OS][OS][64];          // one deposit row, phase split
+    __shared__ float D[NN][OS][OS][64];         // one layer, NN deposit rows, phase split
     __shared__ double tile[TH][TW];
-    __shared__ double P[2][4][64];
+    __shared__ double P[2][NJ][64];
     __shared__ int kst[NCOL + 1];
     __shared__ int tlist[kMaxTileTraces];
-    __shared__ int flags[2][4][OS];
+    __shared__ int flagw[2];
     __shared__ int sh_count, sh_item, sh_qmin, sh_qmax;
+    __shared__ float sh_touch[kTableThreads];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
+    const int clane = lane < TW ? lane : TW - 1;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
 
     for (int iter = 0;; ++iter) {
@@ -128,8 +136,15 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
             const double scale = Tp->thr * flux_scale;
             gptr<ST> spec = as_global((const ST *)as_const(Fp->spec)[Tp->slot]);
             const int k0 = sg.k0, k1 = sg.k1;
-            double ua = fma(horner<DX>(cxr, fma((double)k0, dt, t0)), (double)OS, UC);
-            double ub = fma(horner<DX>(cxr, fma((double)(k1 - 1), dt, t0)), (double)OS, UC);
+            const double ua = fma(horner<DX>(cxr, fma((double)k0, dt, t0)), (double)OS, UC);
+            const double ub = fma(horner<DX>(cxr, fma((double)(k1 - 1), dt, t0)), (double)OS, UC);
+            const double kspan = (double)(k1 - 1 - k0);
+            const double inv_slope = ub > ua ? kspan / (ub - ua) : 0.0;  // samples per slot
+            const bool multi = (sg.cx0 != sg.cx1) | (sg.cy0 != sg.cy1);
+            // pull this item's spectrum into L2 while the column search runs
+            float touch = 0.0f;
+            for (int kk = k0 + 32 * tid; kk < k1; kk += 32 * kTableThreads)
+                touch += (float)spec_at(spec, kk);
 
             for (int cyc = sg.cy0; cyc <= sg.cy1; ++cyc)
             for (int cxc = sg.cx0; cxc <= sg.cx1; ++cxc) {
@@ -142,16 +157,13 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
                 auto search = [&](int qq) -> int {
                     if ((double)qq <= ua) return k0;
                     if ((double)qq > ub) return k1;
-                    double kk = (double)k0 + ((double)qq - ua) / (ub - ua) * (double)(k1 - 1 - k0);
+                    // secant steps on the (nearly linear) slot index, then exact fix-up
+                    double kk = (double)k0 + ((double)qq - ua) * inv_slope;
                     for (int it = 0; it < 2; ++it) {
-                        double t = fma(kk, dt, t0), dx;
-                        double x = horner_d<DX>(cxr, t, &dx);
-                        double u = fma(x, (double)OS, UC);
-                        double du = (double)OS * dx * dt;
-                        if (du > 0.0) kk -= (u - (double)qq) / du;
                         kk = fmin(fmax(kk, (double)k0), (double)(k1 - 1));
+                        kk -= (u_of((int)kk) - (double)qq) * inv_slope;
                     }
-                    int k = (int)ceil(kk);
+                    int k = (int)ceil(fmin(fmax(kk, (double)k0), (double)(k1 - 1)));
                     k = min(max(k, k0 + 1), k1 - 1);
                     int guard = 0;
                     while (k < k1 && u_of(k) < (double)qq && guard < 256) { ++k; ++guard; }
@@ -168,14 +180,30 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
                     for (int lr = 0; lr < 2; ++lr)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) W[l][lr][r][tid] = 0.0f;
+                if (tid < 2) flagw[tid] = 0;
                 __syncthreads();
 
-                // ---- 2. deposits of this column's samples
+                // ---- 2. this column's samples, in order.  Within one row run the
+                // 16 deposits (2 x-slots x 2 rows x 4 nodes) are polynomials of
+                // degree <= 2 in the sub-slot phases (rx, ry), because the CIC
+                // weights and the node weights are both affine in them; so the
+                // run keeps the 9 moments sum phi rx^a ry^b (FP64) and turns
+                // them into deposits when the row changes.
                 const int ks = kst[tid], ke = kst[tid + 1];
-                double a[16];
+                int nbx, nby;
+                double ax0, ax1, ay0, ay1;
+                cell_line(cxc, gsx, gxn, &nbx, &ax0, &ax1);
+                cell_line(cyc, gsy, gyn, &nby, &ay0, &ay1);
+                // fx = ax0 + ax1 * x with x = (q + rx - UC) / OS
+                const double fxa = fma(ax1, ((double)q - UC) / OS, ax0), fxb = ax1 / OS;
+                const double fyb = ay1 / OS;
+                double m[3][3];
 #pragma unroll
-                for (int e = 0; e < 16; ++e) a[e] = 0.0;
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) m[a][b] = 0.0;
                 int runQy = kNone, rb = kNone;
+                bool run_in = false;
                 int qmin = 0x7fffffff, qmax = -0x7fffffff;
                 auto flush = [&]() {
                     int o = runQy - rb;
@@ -183,146 +211,184 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
                         atomicOr(err, kErrRowWindow);
                         return;
                     }
+                    if (run_in) {
+                        qmin = min(qmin, runQy);
+                        qmax = max(qmax, runQy);
+                    }
+                    const double fya = fma(ay1, ((double)runQy - UC) / OS, ay0);
+                    // polynomial coefficients (in rho) of cic x node weight
+                    double X[2][2][3], Y[2][2][3];
+                    auto coef = [](double a, double b, double c[2][2][3]) {
+                        c[0][1][0] = a;       c[0][1][1] = b - a;       c[0][1][2] = -b;
+                        c[0][0][0] = 1.0 - a; c[0][0][1] = a - 1.0 - b; c[0][0][2] = b;
+                        c[1][1][0] = 0.0;     c[1][1][1] = a;           c[1][1][2] = b;
+                        c[1][0][0] = 0.0;     c[1][0][1] = 1.0 - a;     c[1][0][2] = -b;
+                    };
+                    coef(fxa, fxb, X);
+                    coef(fya, fyb, Y);
+                    double Tm[2][2][3];
+#pragma unroll
+                    for (int r = 0; r < 2; ++r)
+#pragma unroll
+                        for (int ny = 0; ny < 2; ++ny)
+#pragma unroll
+                            for (int a = 0; a < 3; ++a)
+                                Tm[r][ny][a] = fma(Y[r][ny][2], m[a][2],
+                                                   fma(Y[r][ny][1], m[a][1], Y[r][ny][0] * m[a][0]));
 #pragma unroll
                     for (int l = 0; l < 4; ++l)
 #pragma unroll
                         for (int lr = 0; lr < 2; ++lr)
 #pragma unroll
                             for (int r = 0; r < 2; ++r) {
-                                int e = ((lr * 2 + (l & 1)) * 2 + r) * 2 + (l >> 1);
-                                W[l][lr][o + r][tid] += (float)(a[e] * scale);
+                                const int nx = l & 1, ny = l >> 1;
+                                double d = fma(X[lr][nx][2], Tm[r][ny][2],
+                                               fma(X[lr][nx][1], Tm[r][ny][1],
+                                                   X[lr][nx][0] * Tm[r][ny][0]));
+                                W[l][lr][o + r][tid] += (float)(d * scale);
                             }
                 };
                 double sv_next = ks < ke ? spec_at(spec, ks) : 0.0;
+                const double UCq = UC - (double)q;
                 for (int k = ks; k < ke; ++k) {
                     double sv = sv_next;
                     if (k + 1 < ke) sv_next = spec_at(spec, k + 1);
                     double t = fma((double)k, dt, t0);
                     double x = horner<DX>(cxr, t);
                     double y = horner<DY>(cyr, t);
-                    double rx = fma(x, (double)OS, UC) - (double)q;
+                    double rx = fma(x, (double)OS, UCq);
                     double vy = fma(y, (double)OS, UC);
                     double fly = floor(vy);
                     int Qy = (int)fly;
                     double ry = vy - fly;
-                    double fx, fy;
-                    int cxs = node_cell(x, gsx, gxn, &fx);
-                    int cys = node_cell(y, gsy, gyn, &fy);
-                    bool in = (cxs == cxc) & (cys == cyc);
+                    bool in = true;
+                    if (multi) in = (ext_cell(x, gsx, gxn) == cxc) & (ext_cell(y, gsy, gyn) == cyc);
                     double phi = in ? sv : 0.0;
                     if (Qy != runQy) {
                         if (runQy != kNone) {
                             flush();
 #pragma unroll
-                            for (int e = 0; e < 16; ++e) a[e] = 0.0;
+                            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                                for (int b = 0; b < 3; ++b) m[a][b] = 0.0;
                         }
                         if (rb == kNone) rb = Qy - 1;
                         runQy = Qy;
+                        run_in = false;
                     }
-                    if (in) {
-                        qmin = min(qmin, Qy);
-                        qmax = max(qmax, Qy);
-                    }
-                    // x factors [lr][node x], y factors [row][node y]
-                    double p1 = phi * rx, p0 = phi - p1;
-                    double xv[2][2], yv[2][2];
-                    xv[0][1] = p0 * fx; xv[0][0] = p0 - xv[0][1];
-                    xv[1][1] = p1 * fx; xv[1][0] = p1 - xv[1][1];
-                    double e1 = ry, e0 = 1.0 - ry;
-                    yv[0][1] = e0 * fy; yv[0][0] = e0 - yv[0][1];
-                    yv[1][1] = e1 * fy; yv[1][0] = e1 - yv[1][1];
-#pragma unroll
-                    for (int lr = 0; lr < 2; ++lr)
-#pragma unroll
-                        for (int nx = 0; nx < 2; ++nx)
-#pragma unroll
-                            for (int r = 0; r < 2; ++r)
-#pragma unroll
-                                for (int ny = 0; ny < 2; ++ny) {
-                                    int e = ((lr * 2 + nx) * 2 + r) * 2 + ny;
-                                    a[e] = fma(xv[lr][nx], yv[r][ny], a[e]);
-                                }
+                    run_in |= in;
+                    const double e1 = phi * ry, e2 = e1 * ry, rx2 = rx * rx;
+                    m[0][0] += phi;
+                    m[0][1] += e1;
+                    m[0][2] += e2;
+                    m[1][0] = fma(phi, rx, m[1][0]);
+                    m[1][1] = fma(e1, rx, m[1][1]);
+                    m[1][2] = fma(e2, rx, m[1][2]);
+                    m[2][0] = fma(phi, rx2, m[2][0]);
+                    m[2][1] = fma(e1, rx2, m[2][1]);
+                    m[2][2] = fma(e2, rx2, m[2][2]);
                 }
                 if (runQy != kNone) flush();
                 rbase[tid] = rb;
+                sh_touch[tid] = touch;
                 if (qmin <= qmax) {
                     atomicMin(&sh_qmin, qmin);
                     atomicMax(&sh_qmax, qmax);
                 }
-                if (tid < OS * 4 * 2) ((int *)flags)[tid] = 0;
                 __syncthreads();
 
-                // ---- 3. stencils, one deposit row at a time
+                // ---- 3. stencils: chunks of NN deposit rows; per node layer the
+                // slots are densified, then each wave applies the taps of its
+                // quarter of the slot offsets to all NN rows (one scalar tap
+                // load feeds NN x DD FMAs); the four partial sums are added
+                // into the FP64 tile in a fixed order.
                 const int qlo = uniform_i(sh_qmin), qhi = uniform_i(sh_qmax) + 1;
                 if (qlo > qhi) continue;  // no sample of this cell here (uniform)
                 const int nlo = floordiv(qlo, OS), nhi = floordiv(qhi, OS);
                 const int nb = max(nlo, Y0 - (DD - 1));
                 const int ne = min(nhi, Y0 + TH - 1);
                 if (nb > ne) continue;
-                const int nlast = min(ne + DD - 1, Y0 + TH - 1);
-                const int mx = min(cxc + (wv & 1), gxn - 1);
-                const int my = min(cyc + (wv >> 1), gyn - 1);
-                cptr<double> taps = as_const(Fp->tb) + (size_t)(my * gxn + mx) * NODE;
-                double acc[DD];
+                for (int nc = nb; nc <= ne; nc += NN) {
+                    double acc[NJ];
 #pragma unroll
-                for (int d = 0; d < DD; ++d) acc[d] = 0.0;
-                for (int n = nb; n <= nlast; ++n) {
-                    const bool has = n <= ne;
-                    if (has && tid < NSLOT) {
-                        const int sgm = tid;
-                        const int rL = rbase[sgm + 1], rR = rbase[sgm];
+                    for (int d = 0; d < NJ; ++d) acc[d] = 0.0;
+                    for (int L = 0; L < 4; ++L) {
+                        if (tid < NSLOT) {
+                            const int sgm = tid;
+                            const int rL = rbase[sgm + 1], rR = rbase[sgm];
+                            int bits = 0;
 #pragma unroll
-                        for (int p = 0; p < OS; ++p) {
-                            const int r = OS * n + p;
-                            const int oL = r - rL, oR = r - rR;
-                            const bool okL = (unsigned)oL < 4u, okR = (unsigned)oR < 4u;
+                            for (int nn = 0; nn < NN; ++nn)
 #pragma unroll
-                            for (int l = 0; l < 4; ++l) {
-                                float vL = okL ? W[l][0][oL & 3][sgm + 1] : 0.0f;
-                                float vR = okR ? W[l][1][oR & 3][sgm] : 0.0f;
-                                float d = vL + vR;
-                                D[l][p][sgm & 3][sgm >> 2] = d;
-                                if (d != 0.0f) flags[n & 1][l][p] = 1;
+                                for (int p = 0; p < OS; ++p) {
+                                    const int r = OS * (nc + nn) + p;
+                                    const int oL = r - rL, oR = r - rR;
+                                    float vL = (unsigned)oL < 4u ? W[L][0][oL & 3][sgm + 1] : 0.0f;
+                                    float vR = (unsigned)oR < 4u ? W[L][1][oR & 3][sgm] : 0.0f;
+                                    float d = vL + vR;
+                                    D[nn][p][sgm & 3][sgm >> 2] = d;
+                                    bits |= (d != 0.0f) ? (1 << (nn * OS + p)) : 0;
+                                }
+                            if (bits) atomicOr(&flagw[L & 1], bits);
+                        }
+                        __syncthreads();
+                        const int fw = uniform_i(flagw[L & 1]);
+                        if (tid == 0) flagw[(L + 1) & 1] = 0;
+                        if (fw) {
+                            const int mx = min(nbx + (L & 1), gxn - 1);
+                            const int my = min(nby + (L >> 1), gyn - 1);
+                            cptr<double> taps = as_const(Fp->tb) + (size_t)(my * gxn + mx) * NODE;
+#pragma unroll
+                            for (int p = 0; p < OS; ++p) {
+                                int pm = 0;
+#pragma unroll
+                                for (int nn = 0; nn < NN; ++nn) pm |= (fw >> (nn * OS + p)) & 1;
+                                if (!pm) continue;
+                                for (int ss = 0; ss < SQ; ++ss) {
+                                    const int s = wv * SQ + ss;
+                                    if (s >= NS) break;
+                                    cptr<double> tp = taps + (p * NS + s) * DD;
+                                    double tv[DD];
+#pragma unroll
+                                    for (int dd = 0; dd < DD; ++dd) tv[dd] = tp[dd];
+#pragma unroll
+                                    for (int nn = 0; nn < NN; ++nn) {
+                                        if (!((fw >> (nn * OS + p)) & 1)) continue;
+                                        double d = (double)D[nn][p][s & 3][clane + (s >> 2)];
+#pragma unroll
+                                        for (int dd = 0; dd < DD; ++dd) {
+                                            if (p == 0 && dd == DD - 1) continue;  // zero tap row
+                                            acc[nn + dd] = fma(d, tv[dd], acc[nn + dd]);
+                                        }
+                                    }
+                                }
                             }
                         }
+                        __syncthreads();
                     }
-                    if (n > nb && tid < TW) {
-                        int j = n - 1 - Y0;
-                        if (j >= 0)
-                            tile[j][tid] += ((P[(n - 1) & 1][0][tid] + P[(n - 1) & 1][1][tid]) +
-                                             P[(n - 1) & 1][2][tid]) + P[(n - 1) & 1][3][tid];
+                    // fixed-order sum of the four partials: (w0 + w2) + (w1 + w3)
+                    if (wv >= 2) {
+#pragma unroll
+                        for (int d = 0; d < NJ; ++d) P[wv - 2][d][lane] = acc[d];
                     }
                     __syncthreads();
-                    if (has) {
+                    if (wv < 2) {
 #pragma unroll
-                        for (int p = 0; p < OS; ++p) {
-                            if (uniform_i(flags[n & 1][wv][p]) == 0) continue;
-                            cptr<double> tp = taps + p * NS * DD;
-#pragma unroll 1
-                            for (int s = 0; s < NS; ++s) {
-                                int m = lane + (s >> 2);
-                                double d = (double)D[wv][p][s & 3][m < 64 ? m : 63];
+                        for (int d = 0; d < NJ; ++d) acc[d] += P[wv][d][lane];
+                    }
+                    __syncthreads();
+                    if (wv == 1) {
 #pragma unroll
-                                for (int dd = 0; dd < DD; ++dd)
-                                    acc[dd] = fma(d, tp[s * DD + dd], acc[dd]);
-                            }
+                        for (int d = 0; d < NJ; ++d) P[0][d][lane] = acc[d];
+                    }
+                    __syncthreads();
+                    if (wv == 0 && lane < TW) {
+#pragma unroll
+                        for (int d = 0; d < NJ; ++d) {
+                            const int j = nc + d - Y0;
+                            if (j >= 0 && j < TH) tile[j][lane] += acc[d] + P[0][d][lane];
                         }
                     }
-                    if (tid == 0) {
-#pragma unroll
-                        for (int e = 0; e < 4 * OS; ++e) ((int *)flags[(n + 1) & 1])[e] = 0;
-                    }
-                    P[n & 1][wv][lane] = acc[0];
-#pragma unroll
-                    for (int d = 0; d < DD - 1; ++d) acc[d] = acc[d + 1];
-                    acc[DD - 1] = 0.0;
-                    __syncthreads();
-                }
-                if (tid < TW) {
-                    int j = nlast - Y0;
-                    if (j >= 0)
-                        tile[j][tid] += ((P[nlast & 1][0][tid] + P[nlast & 1][1][tid]) +
-                                         P[nlast & 1][2][tid]) + P[nlast & 1][3][tid];
                 }
                 __syncthreads();
             }
