@@ -66,6 +66,79 @@ def cpu_baseline(sc):
             "frames_per_s": (upd / dt) / sc.updates()}
 
 
+def serve_bench(E, P, torch, ctx, c1, ld1, specs1, n_req, rate, log):
+    """Served mix (C0 : C1 : C4 = 0.68 : 0.30 : 0.02) with Poisson arrivals;
+    format / PSF tables and spectra resident; latency submit -> done."""
+    import threading
+    from workloads import scene
+    log("building c0 and c4 workloads for the serve mix")
+    c0, c4 = scene("c0"), scene("c4")
+    ld0, ld4 = P.Loaded(ctx, c0), P.Loaded(ctx, c4)
+    sp0 = [torch.from_numpy(s).to("cuda") for s in c0.spectra]
+    sp4 = [torch.from_numpy(s).to("cuda") for s in c4.spectra]
+    kinds = {"c0": (c0, ld0, sp0, E.E2E_F64, torch.float64, E.E2E_F64),
+             "c1": (c1, ld1, specs1, E.E2E_F32, torch.float32, E.E2E_F32),
+             "c4": (c4, ld4, sp4, E.E2E_F32, torch.float32, E.E2E_F32)}
+    rng = np.random.Generator(np.random.PCG64(777))
+    names = rng.choice(["c0", "c1", "c4"], size=n_req, p=[0.68, 0.30, 0.02])
+    gaps = rng.exponential(1.0 / rate, size=n_req)
+    pool = {k: [torch.empty((v[0].ny, v[0].nx), dtype=v[4], device="cuda") for _ in range(8)]
+            for k, v in kinds.items()}
+    E.e2e_serve_start(ctx, max_inflight=8, max_queue=512, n_streams=3, max_batch=4)
+    torch.cuda.synchronize()
+    tickets, keep = [None] * n_req, []
+    sem = {k: threading.Semaphore(8) for k in kinds}
+    slot = {k: 0 for k in kinds}
+    done_evt = []
+
+    def submitter():
+        t0 = time.perf_counter()
+        tnext = t0
+        for i, nm in enumerate(names):
+            tnext += gaps[i]
+            while time.perf_counter() < tnext:
+                time.sleep(min(0.002, max(0.0, tnext - time.perf_counter())))
+            sc, ld, sp, sdt, tdt, odt = kinds[nm]
+            sem[nm].acquire()
+            out = pool[nm][slot[nm] % 8]
+            slot[nm] += 1
+            r, k = P.make_req(ld, [s.data_ptr() for s in sp], sdt, out.data_ptr(), odt,
+                              spectra_on_device=True, out_on_device=True,
+                              rv_mps=float(rng.uniform(-10, 10)))
+            keep.append((r, k))
+            tickets[i] = E.e2e_serve_submit(ctx, r)
+        done_evt.append(time.perf_counter())
+
+    th = threading.Thread(target=submitter)
+    t_start = time.perf_counter()
+    th.start()
+    lat = {k: [] for k in kinds}
+    allat = []
+    for i in range(n_req):
+        while tickets[i] is None:
+            time.sleep(0.0005)
+        code, st = E.e2e_serve_poll(ctx, tickets[i], -1)
+        sem[names[i]].release()
+        ms = (st.t_done_us - st.t_submit_us) / 1e3
+        lat[names[i]].append(ms)
+        allat.append(ms)
+    t_end = time.perf_counter()
+    th.join()
+    E.e2e_serve_stop(ctx)
+    ld0.free()
+    ld4.free()
+    upd = {"c0": c0.updates(), "c1": c1.updates(), "c4": c4.updates()}
+    tot_upd = sum(upd[n] for n in names)
+    return {"requests": n_req, "rate_per_s": rate,
+            "mix": {k: int(np.sum(names == k)) for k in kinds},
+            "frames_per_s": n_req / (t_end - t_start),
+            "updates_per_s": tot_upd / (t_end - t_start),
+            "latency_ms_p50": float(np.percentile(allat, 50)),
+            "latency_ms_p99": float(np.percentile(allat, 99)),
+            "by_kind_ms_p50_p99": {k: [float(np.percentile(v, 50)), float(np.percentile(v, 99))]
+                                   for k, v in lat.items() if v}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +147,9 @@ def main():
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--plain-frames", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=120,
+                    help="served HIRES-shaped mix; 0 skips it")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrivals per second")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -176,6 +252,13 @@ def main():
            "latency_ms_p99": float(np.percentile(lat, 99)),
            "plan_ms_per_launch": ms_plan / max(n_plan, 1),
            "roofline": roof}
+    if args.serve_requests > 0:
+        res["serve"] = serve_bench(E, P, torch, ctx, sc, ld, specs, args.serve_requests,
+                                   args.serve_rate, log)
+        res["latency_ms_p50"] = res["serve"]["latency_ms_p50"]
+        res["latency_ms_p99"] = res["serve"]["latency_ms_p99"]
+        res["latency_source"] = "served HIRES-shaped mix, submit to done"
+        res["plain_latency_ms_p50"] = float(np.percentile(lat, 50))
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(sc)

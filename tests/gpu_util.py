@@ -39,10 +39,10 @@ def request_for(loaded, scene, specs, sdt, out, odt, req=None, **kw):
                       spectra_on_device=True, out_on_device=True, **r)
 
 
-def render(scene, req=None, loaded=None, out_dtype=None, **kw):
-    """One frame through e2e_render; returns (numpy frame, loaded)."""
+def render(scene, req=None, loaded=None, out_dtype=None, context=None, **kw):
+    """One frame through e2e_render (on `context`, default the shared one)."""
     import torch
-    c = ctx()
+    c = context if context is not None else ctx()
     own = loaded is None
     loaded = loaded or P.Loaded(c, scene)
     specs, sdt = device_spectra(scene)

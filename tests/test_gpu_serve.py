@@ -53,7 +53,8 @@ def test_serve_mix_equals_alone():
     # references: alone, plain renderer
     refs = []
     for name, rv, fs in plan:
-        refs.append(gu.render(scs[name], Request(rv_mps=rv, flux_scale=fs), loaded=lds[name]))
+        refs.append(gu.render(scs[name], Request(rv_mps=rv, flux_scale=fs), loaded=lds[name],
+                              context=ctx))
     E.e2e_serve_start(ctx, max_inflight=6, max_queue=64, n_streams=3, max_batch=4)
     outs = [None] * len(plan)
     tickets = [None] * len(plan)
