@@ -243,17 +243,11 @@ extern "C" e2e_status e2e_format_load(e2e_ctx *ctx, const e2e_trace_desc *tr, in
 
 // Taps of one node: B(vy, vx) = sum of the table over the os x os cells
 // starting at (vx, vy) (cells outside the table are zero), stored as
-// tb[p][s][dd] = B(os dd - p, kw - 1 - s).
+// tb[s][p][dd] = B(os dd - p, kw - 1 - s): the taps of one slot offset s are
+// contiguous, which is the order the stencil streams them in.
 static void node_taps(const float *K, int kw, double *tb)
 {
     const int OS = kOS, NS = kw + OS - 1, DD = (kw + OS - 2) / OS + 1;
-    std::vector<double> pre((size_t)(kw + 1) * (kw + 1), 0.0);  // 2D prefix sums
-    for (int b = 0; b < kw; ++b)
-        for (int a = 0; a < kw; ++a)
-            pre[(size_t)(b + 1) * (kw + 1) + a + 1] = (double)K[(size_t)b * kw + a] +
-                                                      pre[(size_t)b * (kw + 1) + a + 1] +
-                                                      pre[(size_t)(b + 1) * (kw + 1) + a] -
-                                                      pre[(size_t)b * (kw + 1) + a];
     auto box = [&](int vy, int vx) {
         int y0 = std::max(vy, 0), y1 = std::min(vy + OS, kw);
         int x0 = std::max(vx, 0), x1 = std::min(vx + OS, kw);
@@ -264,11 +258,10 @@ static void node_taps(const float *K, int kw, double *tb)
             for (int a = x0; a < x1; ++a) s += (double)K[(size_t)b * kw + a];
         return s;
     };
-    (void)pre;
-    for (int p = 0; p < OS; ++p)
-        for (int s = 0; s < NS; ++s)
+    for (int s = 0; s < NS; ++s)
+        for (int p = 0; p < OS; ++p)
             for (int dd = 0; dd < DD; ++dd)
-                tb[((size_t)p * NS + s) * DD + dd] = box(OS * dd - p, kw - 1 - s);
+                tb[((size_t)s * OS + p) * DD + dd] = box(OS * dd - p, kw - 1 - s);
 }
 
 extern "C" e2e_status e2e_psf_load(e2e_ctx *ctx, const e2e_psf_desc *d, e2e_psf_id *out)

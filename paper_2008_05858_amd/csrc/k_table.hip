@@ -16,14 +16,18 @@
 // its pixels exactly once; no global atomics.  For every trace reaching the
 // tile (ascending trace order, then node cell) it
 //   1. gives each thread one slot column and finds that column's samples by
-//      a Newton search on the FP64 format polynomial;
-//   2. walks those samples in order (FP64 positions, FP64 register sums of
-//      the 16 deposits, flushed to the column's private 4-row LDS window);
-//   3. per deposit row, densifies the slots and applies the node stencils,
-//      one wave per node, taps read through the scalar cache, FP64 sums in a
-//      rolling register window, then adds the four node partials into the
-//      FP64 LDS tile in node order.
+//      a secant search on the FP64 format polynomial;
+//   2. walks those samples in order (spectrum values prefetched in groups,
+//      FP64 positions, FP64 moment sums per row run) into the column's
+//      private 4-row deposit window held in registers;
+//   3. for each band of 3 deposit rows that holds data, lays the windows out
+//      as a dense band in LDS, and each wave applies the node stencils of a
+//      quarter of the slot offsets (taps streamed through the scalar cache,
+//      FP64 sums); the four wave partials are added into the FP64 LDS tile in
+//      a fixed order.
 // The summation order is fixed, so reruns are bitwise identical.
+#include <type_traits>
+
 #include "dev_common.h"
 
 namespace e2e {
@@ -41,35 +45,40 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
     constexpr int NCOL = kTableThreads;        // slot columns per tile
     constexpr int TW = (NCOL - KW) / OS;       // tile width in pixels
     constexpr int TH = kTableTH;
-    constexpr int NSLOT = NCOL - 1;            // slots that reach the tile
     constexpr int NS = KW + OS - 1;            // slots per pixel column
     constexpr int DD = (KW + OS - 2) / OS + 1; // pixel rows per deposit row
     constexpr int NODE = OS * NS * DD;         // taps per node
-    constexpr int SU = (NS % 5 == 0) ? 5 : ((NS % 3 == 0) ? 3 : 1);  // stencil unroll
     constexpr double UC = 0.5 * (OS - KW);
     static_assert(OS * TW + KW == NCOL, "tile geometry");
     static_assert(TW <= 64, "one wave spans the tile width");
 
-    constexpr int NN = KW <= 32 ? 4 : 2;       // deposit rows per stencil chunk
-    constexpr int NJ = NN + DD - 1;            // output rows a chunk reaches
-    constexpr int SQ = (NS + 3) / 4;           // stencil columns per wave
-    static_assert(NN * OS <= 16, "flag bits");
+    constexpr int NB = 3;                      // deposit rows per band
+    constexpr int NJ = DD + 1;                 // output rows a band reaches
+    constexpr int SQ = (NS + 3) / 4;           // slot offsets per wave
+    constexpr int PQ = 65;                     // padded phase block of a band row
+    constexpr int PR = 4 * PQ;                 // band row stride (floats)
+    constexpr int BANDF = 4 * NB * PR;         // floats of the band
+    constexpr int PARTF = 3 * NJ * 64 * 2;     // floats of the wave partials
+    constexpr int BUFF = BANDF > PARTF ? BANDF : PARTF;
+    static_assert(NB <= 4, "a band row range maps to two output offsets");
 
-    __shared__ float W[4][2][4][NCOL];          // per-column deposit windows
-    __shared__ int rbase[NCOL];                 // window base row per column
-    __shared__ float D[NN][OS][OS][64];         // one layer, NN deposit rows, phase split
+    // The band (4 node layers x NR rows x slots, slot c at (c & 3) * PQ + c / 4
+    // so a wave's stencil reads are consecutive) and, once the stencil has read
+    // it, the partial sums of waves 1..3.
+    __shared__ double bandbuf[BUFF / 2];
     __shared__ double tile[TH][TW];
-    __shared__ double P[2][NJ][64];
     __shared__ int kst[NCOL + 1];
     __shared__ int tlist[kMaxTileTraces];
-    __shared__ int flagw[2];
-    __shared__ int sh_count, sh_item, sh_qmin, sh_qmax;
-    __shared__ float sh_touch[kTableThreads];
+    __shared__ int sh_count, sh_item, sh_qmin, sh_qmax, sh_touch;
 
+    float *band = reinterpret_cast<float *>(bandbuf);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int clane = lane < TW ? lane : TW - 1;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int pc = (tid & 3) * PQ + (tid >> 2);              // own slot in a band row
+    const int pcl = ((tid + NCOL - 1) & 3) * PQ + ((tid - 1) >> 2);  // slot tid - 1
+    if (tid == 0) sh_touch = 0;
 
     for (int iter = 0;; ++iter) {
         int fi, tile_id;
@@ -91,8 +100,6 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
         const int tx = tile_id % Fp->ntx, ty = tile_id / Fp->ntx;
         const int X0 = tx * TW, Y0 = ty * TH;
         const SegDev *segs = Fp->segs + (size_t)tx * ntr;
-        const double beta = Fp->beta, flux_scale = Fp->flux_scale, gsx = Fp->gsx, gsy = Fp->gsy;
-        const int gxn = Fp->gx, gyn = Fp->gy;
 
         // ---- traces reaching this tile, ascending
         if (tid < 64) {
@@ -120,34 +127,49 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
 
         for (int li = 0; li < count; ++li) {
             const int tr = uniform_i(tlist[li]);
-            cptr<TraceDev> Tp = as_const(Fp->tr) + tr;
             const SegDev sg = segs[tr];
-            double cxr[DX + 1], cyr[DY + 1];
-#pragma unroll
-            for (int j = 0; j <= DX; ++j) cxr[j] = Tp->cx[j];
-#pragma unroll
-            for (int j = 0; j <= DY; ++j) cyr[j] = Tp->cy[j];
-            TraceDev Tl;
-            Tl.lmin = Tp->lmin;
-            Tl.lmax = Tp->lmax;
-            Tl.n = Tp->n;
-            double t0, dt;
-            trace_affine(Tl, beta, &t0, &dt);
-            const double scale = Tp->thr * flux_scale;
-            gptr<ST> spec = as_global((const ST *)as_const(Fp->spec)[Tp->slot]);
             const int k0 = sg.k0, k1 = sg.k1;
-            const double ua = fma(horner<DX>(cxr, fma((double)k0, dt, t0)), (double)OS, UC);
-            const double ub = fma(horner<DX>(cxr, fma((double)(k1 - 1), dt, t0)), (double)OS, UC);
-            const double kspan = (double)(k1 - 1 - k0);
-            const double inv_slope = ub > ua ? kspan / (ub - ua) : 0.0;  // samples per slot
             const bool multi = (sg.cx0 != sg.cx1) | (sg.cy0 != sg.cy1);
-            // pull this item's spectrum into L2 while the column search runs
-            float touch = 0.0f;
-            for (int kk = k0 + 32 * tid; kk < k1; kk += 32 * kTableThreads)
-                touch += (float)spec_at(spec, kk);
 
             for (int cyc = sg.cy0; cyc <= sg.cy1; ++cyc)
             for (int cxc = sg.cx0; cxc <= sg.cx1; ++cxc) {
+                cptr<TraceDev> Tp = as_const(Fp->tr) + tr;
+                double cxr[DX + 1], cyr[DY + 1];
+#pragma unroll
+                for (int j = 0; j <= DX; ++j) cxr[j] = Tp->cx[j];
+#pragma unroll
+                for (int j = 0; j <= DY; ++j) cyr[j] = Tp->cy[j];
+                double t0, dt;
+                {
+                    TraceDev Tl;
+                    Tl.lmin = Tp->lmin;
+                    Tl.lmax = Tp->lmax;
+                    Tl.n = Tp->n;
+                    trace_affine(Tl, Fp->beta, &t0, &dt);
+                }
+                // the per-sample polynomial arithmetic reads these from vector
+                // registers: wave-uniform, but the scalar file is needed elsewhere
+#pragma unroll
+                for (int j = 0; j <= DX; ++j) asm volatile("" : "+v"(cxr[j]));
+#pragma unroll
+                for (int j = 0; j <= DY; ++j) asm volatile("" : "+v"(cyr[j]));
+                asm volatile("" : "+v"(t0), "+v"(dt));
+                const double scale = Tp->thr * Fp->flux_scale;
+                gptr<ST> spec = as_global((const ST *)as_const(Fp->spec)[Tp->slot]);
+                const double gsx = Fp->gsx, gsy = Fp->gsy;
+                const int gxn = Fp->gx, gyn = Fp->gy;
+                const double ua = fma(horner<DX>(cxr, fma((double)k0, dt, t0)), (double)OS, UC);
+                const double ub = fma(horner<DX>(cxr, fma((double)(k1 - 1), dt, t0)), (double)OS, UC);
+                const double inv_slope = ub > ua ? (double)(k1 - 1 - k0) / (ub - ua) : 0.0;
+
+                // pull this item's spectrum into L2 while the column search runs
+                if (cyc == sg.cy0 && cxc == sg.cx0) {
+                    float touch = 0.0f;
+                    for (int kk = k0 + 32 * tid; kk < k1; kk += 32 * kTableThreads)
+                        touch += (float)spec_at(spec, kk);
+                    if (touch == -1.0f) sh_touch = 1;  // keeps the loads
+                }
+
                 // ---- 1. samples of each slot column: first k with u(k) >= q
                 const int q = OS * X0 - KW + tid;
                 auto u_of = [&](int k) {
@@ -174,13 +196,6 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
                 kst[tid] = search(q);
                 if (tid == NCOL - 1) kst[NCOL] = search(q + 1);
                 if (tid == 0) { sh_qmin = 0x7fffffff; sh_qmax = -0x7fffffff; }
-#pragma unroll
-                for (int l = 0; l < 4; ++l)
-#pragma unroll
-                    for (int lr = 0; lr < 2; ++lr)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) W[l][lr][r][tid] = 0.0f;
-                if (tid < 2) flagw[tid] = 0;
                 __syncthreads();
 
                 // ---- 2. this column's samples, in order.  Within one row run the
@@ -188,7 +203,8 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
                 // degree <= 2 in the sub-slot phases (rx, ry), because the CIC
                 // weights and the node weights are both affine in them; so the
                 // run keeps the 9 moments sum phi rx^a ry^b (FP64) and turns
-                // them into deposits when the row changes.
+                // them into deposits when the row changes.  Deposits go to the
+                // column's 4-row window wr[layer][x-slot][row] (rows rb..rb+3).
                 const int ks = kst[tid], ke = kst[tid + 1];
                 int nbx, nby;
                 double ax0, ax1, ay0, ay1;
@@ -197,6 +213,13 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
                 // fx = ax0 + ax1 * x with x = (q + rx - UC) / OS
                 const double fxa = fma(ax1, ((double)q - UC) / OS, ax0), fxb = ax1 / OS;
                 const double fyb = ay1 / OS;
+                float wr[4][2][4];
+#pragma unroll
+                for (int l = 0; l < 4; ++l)
+#pragma unroll
+                    for (int lr = 0; lr < 2; ++lr)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) wr[l][lr][r] = 0.0f;
                 double m[3][3];
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
@@ -206,7 +229,7 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
                 bool run_in = false;
                 int qmin = 0x7fffffff, qmax = -0x7fffffff;
                 auto flush = [&]() {
-                    int o = runQy - rb;
+                    const int o = runQy - rb;
                     if (o < 0 || o > 2) {
                         atomicOr(err, kErrRowWindow);
                         return;
@@ -238,21 +261,24 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
 #pragma unroll
                     for (int l = 0; l < 4; ++l)
 #pragma unroll
-                        for (int lr = 0; lr < 2; ++lr)
+                        for (int lr = 0; lr < 2; ++lr) {
+                            const int nx = l & 1, ny = l >> 1;
+                            float dv[2];
 #pragma unroll
                             for (int r = 0; r < 2; ++r) {
-                                const int nx = l & 1, ny = l >> 1;
                                 double d = fma(X[lr][nx][2], Tm[r][ny][2],
                                                fma(X[lr][nx][1], Tm[r][ny][1],
                                                    X[lr][nx][0] * Tm[r][ny][0]));
-                                W[l][lr][o + r][tid] += (float)(d * scale);
+                                dv[r] = (float)(d * scale);
                             }
+                            wr[l][lr][0] += o == 0 ? dv[0] : 0.0f;
+                            wr[l][lr][1] += o == 0 ? dv[1] : (o == 1 ? dv[0] : 0.0f);
+                            wr[l][lr][2] += o == 1 ? dv[1] : (o == 2 ? dv[0] : 0.0f);
+                            wr[l][lr][3] += o == 2 ? dv[1] : 0.0f;
+                        }
                 };
-                double sv_next = ks < ke ? spec_at(spec, ks) : 0.0;
                 const double UCq = UC - (double)q;
-                for (int k = ks; k < ke; ++k) {
-                    double sv = sv_next;
-                    if (k + 1 < ke) sv_next = spec_at(spec, k + 1);
+                auto sample = [&](int k, double sv) {
                     double t = fma((double)k, dt, t0);
                     double x = horner<DX>(cxr, t);
                     double y = horner<DY>(cyr, t);
@@ -287,110 +313,138 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
                     m[2][0] = fma(phi, rx2, m[2][0]);
                     m[2][1] = fma(e1, rx2, m[2][1]);
                     m[2][2] = fma(e2, rx2, m[2][2]);
+                };
+                if (ks < ke) {
+                    // spectrum values four samples ahead (indices clamped into the
+                    // column, so every load is unconditional)
+                    const int kl = ke - 1;
+                    ST v0 = spec[min(ks, kl)], v1 = spec[min(ks + 1, kl)];
+                    ST v2 = spec[min(ks + 2, kl)], v3 = spec[min(ks + 3, kl)];
+                    for (int kb = ks; kb < ke; kb += 4) {
+                        const ST n0 = spec[min(kb + 4, kl)], n1 = spec[min(kb + 5, kl)];
+                        const ST n2 = spec[min(kb + 6, kl)], n3 = spec[min(kb + 7, kl)];
+                        sample(kb, (double)v0);
+                        if (kb + 1 < ke) sample(kb + 1, (double)v1);
+                        if (kb + 2 < ke) sample(kb + 2, (double)v2);
+                        if (kb + 3 < ke) sample(kb + 3, (double)v3);
+                        v0 = n0; v1 = n1; v2 = n2; v3 = n3;
+                    }
+                    flush();
                 }
-                if (runQy != kNone) flush();
-                rbase[tid] = rb;
-                sh_touch[tid] = touch;
                 if (qmin <= qmax) {
                     atomicMin(&sh_qmin, qmin);
                     atomicMax(&sh_qmax, qmax);
                 }
                 __syncthreads();
 
-                // ---- 3. stencils: chunks of NN deposit rows; per node layer the
-                // slots are densified, then each wave applies the taps of its
-                // quarter of the slot offsets to all NN rows (one scalar tap
-                // load feeds NN x DD FMAs); the four partial sums are added
-                // into the FP64 tile in a fixed order.
+                // ---- 3. stencils over bands of NB consecutive deposit rows
+                // (any start).  Deposit row 4n + p reaches output rows
+                // n .. n + DD - 1; a band starting at A spans output rows
+                // A/4 .. A/4 + NJ - 1.
                 const int qlo = uniform_i(sh_qmin), qhi = uniform_i(sh_qmax) + 1;
                 if (qlo > qhi) continue;  // no sample of this cell here (uniform)
-                const int nlo = floordiv(qlo, OS), nhi = floordiv(qhi, OS);
-                const int nb = max(nlo, Y0 - (DD - 1));
-                const int ne = min(nhi, Y0 + TH - 1);
-                if (nb > ne) continue;
-                for (int nc = nb; nc <= ne; nc += NN) {
+                const int rlo = max(qlo, OS * (Y0 - (DD - 1)));
+                const int rhi = min(qhi, OS * (Y0 + TH) - 1);
+                if (rlo > rhi) continue;
+                for (int A = rlo; A <= rhi; A += NB) {
+                    // 3a. the band: right-slot parts of each column's window in its
+                    // own slot, then (after a barrier) the left-slot parts of
+                    // column c + 1 added into slot c
+#pragma unroll
+                    for (int l = 0; l < 4; ++l)
+#pragma unroll
+                        for (int r = 0; r < NB; ++r) band[(l * NB + r) * PR + pc] = 0.0f;
+                    const int ro = rb - A;  // window row 0 in the band
+                    if (rb != kNone) {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if ((unsigned)(ro + j) < (unsigned)NB)
+#pragma unroll
+                                for (int l = 0; l < 4; ++l)
+                                    band[(l * NB + ro + j) * PR + pc] = wr[l][1][j];
+                    }
+                    __syncthreads();
+                    if (rb != kNone && tid > 0) {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if ((unsigned)(ro + j) < (unsigned)NB)
+#pragma unroll
+                                for (int l = 0; l < 4; ++l)
+                                    band[(l * NB + ro + j) * PR + pcl] += wr[l][0][j];
+                    }
+                    __syncthreads();
+
+                    // 3b. stencil: wave wv takes slot offsets s = wv*SQ .. +SQ-1 of
+                    // every node layer; lane = pixel column.  Band row r has
+                    // phase (A + r) & 3 and output offset ((A & 3) + r) >> 2; the
+                    // code is specialised on A & 3 so both are compile-time.
                     double acc[NJ];
 #pragma unroll
                     for (int d = 0; d < NJ; ++d) acc[d] = 0.0;
-                    for (int L = 0; L < 4; ++L) {
-                        if (tid < NSLOT) {
-                            const int sgm = tid;
-                            const int rL = rbase[sgm + 1], rR = rbase[sgm];
-                            int bits = 0;
-#pragma unroll
-                            for (int nn = 0; nn < NN; ++nn)
-#pragma unroll
-                                for (int p = 0; p < OS; ++p) {
-                                    const int r = OS * (nc + nn) + p;
-                                    const int oL = r - rL, oR = r - rR;
-                                    float vL = (unsigned)oL < 4u ? W[L][0][oL & 3][sgm + 1] : 0.0f;
-                                    float vR = (unsigned)oR < 4u ? W[L][1][oR & 3][sgm] : 0.0f;
-                                    float d = vL + vR;
-                                    D[nn][p][sgm & 3][sgm >> 2] = d;
-                                    bits |= (d != 0.0f) ? (1 << (nn * OS + p)) : 0;
-                                }
-                            if (bits) atomicOr(&flagw[L & 1], bits);
-                        }
-                        __syncthreads();
-                        const int fw = uniform_i(flagw[L & 1]);
-                        if (tid == 0) flagw[(L + 1) & 1] = 0;
-                        if (fw) {
+                    const int s0 = wv * SQ;
+                    cptr<double> tbase = as_const(Fp->tb) + (size_t)s0 * OS * DD;
+                    auto stencil = [&](auto cph) {
+                        constexpr int C = decltype(cph)::value;
+#pragma unroll 1
+                        for (int L = 0; L < 4; ++L) {
                             const int mx = min(nbx + (L & 1), gxn - 1);
                             const int my = min(nby + (L >> 1), gyn - 1);
-                            cptr<double> taps = as_const(Fp->tb) + (size_t)(my * gxn + mx) * NODE;
+                            cptr<double> taps = tbase + (size_t)(my * gxn + mx) * NODE;
+#pragma unroll 1
+                            for (int ss = 0; ss < SQ; ++ss) {
+                                const int sl = s0 + ss;
+                                if (sl >= NS) break;  // uniform
+                                const int a = (sl & 3) * PQ + clane + (sl >> 2);
+                                float dv[NB];
+                                double tv[NB][DD];
 #pragma unroll
-                            for (int p = 0; p < OS; ++p) {
-                                int pm = 0;
+                                for (int r = 0; r < NB; ++r) {
+                                    dv[r] = band[(L * NB + r) * PR + a];
+                                    const int p = (C + r) & 3;
 #pragma unroll
-                                for (int nn = 0; nn < NN; ++nn) pm |= (fw >> (nn * OS + p)) & 1;
-                                if (!pm) continue;
-                                for (int ss = 0; ss < SQ; ++ss) {
-                                    const int s = wv * SQ + ss;
-                                    if (s >= NS) break;
-                                    cptr<double> tp = taps + (p * NS + s) * DD;
-                                    double tv[DD];
+                                    for (int dd = 0; dd < DD; ++dd)
+                                        tv[r][dd] = taps[(ss * OS + p) * DD + dd];
+                                }
 #pragma unroll
-                                    for (int dd = 0; dd < DD; ++dd) tv[dd] = tp[dd];
+                                for (int r = 0; r < NB; ++r) {
+                                    const int p = (C + r) & 3, n = (C + r) >> 2;
+                                    const double d = (double)dv[r];
 #pragma unroll
-                                    for (int nn = 0; nn < NN; ++nn) {
-                                        if (!((fw >> (nn * OS + p)) & 1)) continue;
-                                        double d = (double)D[nn][p][s & 3][clane + (s >> 2)];
-#pragma unroll
-                                        for (int dd = 0; dd < DD; ++dd) {
-                                            if (p == 0 && dd == DD - 1) continue;  // zero tap row
-                                            acc[nn + dd] = fma(d, tv[dd], acc[nn + dd]);
-                                        }
+                                    for (int dd = 0; dd < DD; ++dd) {
+                                        if (p == 0 && dd == DD - 1) continue;  // zero tap row
+                                        acc[n + dd] = fma(d, tv[r][dd], acc[n + dd]);
                                     }
                                 }
                             }
                         }
-                        __syncthreads();
+                    };
+                    switch (A & 3) {
+                    case 0: stencil(std::integral_constant<int, 0>()); break;
+                    case 1: stencil(std::integral_constant<int, 1>()); break;
+                    case 2: stencil(std::integral_constant<int, 2>()); break;
+                    default: stencil(std::integral_constant<int, 3>()); break;
                     }
-                    // fixed-order sum of the four partials: (w0 + w2) + (w1 + w3)
-                    if (wv >= 2) {
-#pragma unroll
-                        for (int d = 0; d < NJ; ++d) P[wv - 2][d][lane] = acc[d];
-                    }
+                    // 3c. fixed-order sum of the four partials into the tile
                     __syncthreads();
-                    if (wv < 2) {
+                    double *P = bandbuf;
+                    if (wv > 0) {
 #pragma unroll
-                        for (int d = 0; d < NJ; ++d) acc[d] += P[wv][d][lane];
-                    }
-                    __syncthreads();
-                    if (wv == 1) {
-#pragma unroll
-                        for (int d = 0; d < NJ; ++d) P[0][d][lane] = acc[d];
+                        for (int d = 0; d < NJ; ++d) P[((wv - 1) * NJ + d) * 64 + lane] = acc[d];
                     }
                     __syncthreads();
                     if (wv == 0 && lane < TW) {
+                        const int n0 = (A >> 2) - Y0;
 #pragma unroll
                         for (int d = 0; d < NJ; ++d) {
-                            const int j = nc + d - Y0;
-                            if (j >= 0 && j < TH) tile[j][lane] += acc[d] + P[0][d][lane];
+                            const int j = n0 + d;
+                            if (j >= 0 && j < TH)
+                                tile[j][lane] += ((acc[d] + P[d * 64 + lane]) +
+                                                  P[(NJ + d) * 64 + lane]) +
+                                                 P[(2 * NJ + d) * 64 + lane];
                         }
                     }
+                    __syncthreads();
                 }
-                __syncthreads();
             }
         }
         __syncthreads();
@@ -437,7 +491,9 @@ hipError_t launch_deg(const FrameDev *frames_dev, int degx, int degy, int spec_f
 hipError_t launch_table(const FrameDev *frames_dev, const KernelCfg &cfg, const int2 *work,
                         int n_work, int *counter, int *err, hipStream_t s)
 {
-    int nblocks = work == nullptr ? cfg.plain_tiles : (n_work < 512 ? n_work : 512);
+    const int resident = cfg.kw <= 32 ? 3 : 2;  // workgroups per CU
+    const int cap = 256 * resident;
+    int nblocks = work == nullptr ? cfg.plain_tiles : (n_work < cap ? n_work : cap);
     if (nblocks <= 0) return hipSuccess;
     if (cfg.kw == 32)
         return launch_deg<32>(frames_dev, cfg.degx, cfg.degy, cfg.spec_f64, work, n_work,
