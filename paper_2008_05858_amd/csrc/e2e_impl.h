@@ -39,6 +39,8 @@ struct SegDev {
     int8_t cx0, cx1, cy0, cy1;  // node cells spanned (table path)
 };
 
+static_assert(sizeof(SegDev) == 16, "SegDev is read as one 16-byte word");
+
 // Everything one frame's kernels need; lives in device memory.
 struct FrameDev {
     const TraceDev *tr;

@@ -37,7 +37,7 @@ namespace {
 constexpr int kNone = 0x3fffffff;  // "no row yet"; far from any real row
 
 template <int KW, int DX, int DY, typename ST>
-__global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
+__global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_table(
     const FrameDev *__restrict__ frames, const int2 *__restrict__ work, int n_work,
     int *__restrict__ counter, int *__restrict__ err)
 {
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
     constexpr int NB = 3;                      // deposit rows per band
     constexpr int NJ = DD + 1;                 // output rows a band reaches
     constexpr int SQ = (NS + 3) / 4;           // slot offsets per wave
-    constexpr int PQ = 65;                     // padded phase block of a band row
+    constexpr int PQ = 80;                     // phase block of a band row (bank spread)
     constexpr int PR = 4 * PQ;                 // band row stride (floats)
     constexpr int BANDF = 4 * NB * PR;         // floats of the band
     constexpr int PARTF = 3 * NJ * 64 * 2;     // floats of the wave partials
@@ -69,7 +69,8 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
     __shared__ double tile[TH][TW];
     __shared__ int kst[NCOL + 1];
     __shared__ int tlist[kMaxTileTraces];
-    __shared__ int sh_count, sh_item, sh_qmin, sh_qmax, sh_touch;
+    __shared__ SegDev tseg[kMaxTileTraces];
+    __shared__ int sh_wsum[4], sh_item, sh_qmin, sh_qmax, sh_touch;
 
     float *band = reinterpret_cast<float *>(bandbuf);
     const int tid = threadIdx.x;
@@ -101,33 +102,65 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
         const int X0 = tx * TW, Y0 = ty * TH;
         const SegDev *segs = Fp->segs + (size_t)tx * ntr;
 
-        // ---- traces reaching this tile, ascending
-        if (tid < 64) {
-            int cnt = 0;
-            for (int base = 0; base < ntr; base += 64) {
-                int tr = base + lane;
-                bool ok = false;
-                if (tr < ntr) {
-                    SegDev s = segs[tr];
-                    ok = s.k0 < s.k1 && s.ty0 <= ty && ty <= s.ty1;
-                }
-                unsigned long long m = __ballot(ok);
-                int pos = cnt + __popcll(m & ((1ull << lane) - 1ull));
-                if (ok) {
-                    if (pos < kMaxTileTraces) tlist[pos] = tr;
-                    else atomicOr(err, kErrTileTraces);
-                }
-                cnt += __popcll(m);
+        // ---- traces reaching this tile, ascending: each thread tests a run of
+        // eight traces (one round of loads), a block-wide prefix sum places them
+        int count = 0;
+        for (int pb = 0; pb < ntr; pb += 8 * NCOL) {
+            const int mb = pb + 8 * tid;
+            unsigned bits = 0;
+            SegDev sgv[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                sgv[j] = segs[min(mb + j, ntr - 1)];
+                const bool ok = mb + j < ntr && sgv[j].k0 < sgv[j].k1 && sgv[j].ty0 <= ty &&
+                                ty <= sgv[j].ty1;
+                bits |= ok ? 1u << j : 0u;
             }
-            if (lane == 0) sh_count = min(cnt, kMaxTileTraces);
+            const int cnt = __popc(bits);
+            int x = cnt;  // inclusive scan over the wave
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o);
+                if (lane >= o) x += y;
+            }
+            if (lane == 63) sh_wsum[wv] = x;
+            __syncthreads();
+            int pos = count + x - cnt, tot = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const int v = sh_wsum[w];
+                pos += w < wv ? v : 0;
+                tot += v;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (!((bits >> j) & 1)) continue;
+                if (pos < kMaxTileTraces) {
+                    tlist[pos] = mb + j;
+                    tseg[pos] = sgv[j];
+                } else {
+                    atomicOr(err, kErrTileTraces);
+                }
+                ++pos;
+            }
+            count = min(count + uniform_i(tot), kMaxTileTraces);
+            __syncthreads();
         }
         for (int e = tid; e < TH * TW; e += kTableThreads) tile[e / TW][e % TW] = 0.0;
         __syncthreads();
-        const int count = uniform_i(sh_count);
 
+        float touch = 0.0f;  // prefetch sink
         for (int li = 0; li < count; ++li) {
             const int tr = uniform_i(tlist[li]);
-            const SegDev sg = segs[tr];
+            SegDev sg;
+            {
+                int4 raw = *reinterpret_cast<const int4 *>(&tseg[li]);
+                raw.x = uniform_i(raw.x);
+                raw.y = uniform_i(raw.y);
+                raw.z = uniform_i(raw.z);
+                raw.w = uniform_i(raw.w);
+                __builtin_memcpy(&sg, &raw, sizeof(sg));
+            }
             const int k0 = sg.k0, k1 = sg.k1;
             const bool multi = (sg.cx0 != sg.cx1) | (sg.cy0 != sg.cy1);
 
@@ -162,12 +195,11 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
                 const double ub = fma(horner<DX>(cxr, fma((double)(k1 - 1), dt, t0)), (double)OS, UC);
                 const double inv_slope = ub > ua ? (double)(k1 - 1 - k0) / (ub - ua) : 0.0;
 
-                // pull this item's spectrum into L2 while the column search runs
-                if (cyc == sg.cy0 && cxc == sg.cx0) {
-                    float touch = 0.0f;
+                // the first item pulls its spectrum into L2 while its column
+                // search runs; later items were prefetched by their predecessor
+                if (li == 0 && cyc == sg.cy0 && cxc == sg.cx0) {
                     for (int kk = k0 + 32 * tid; kk < k1; kk += 32 * kTableThreads)
                         touch += (float)spec_at(spec, kk);
-                    if (touch == -1.0f) sh_touch = 1;  // keeps the loads
                 }
 
                 // ---- 1. samples of each slot column: first k with u(k) >= q
@@ -331,7 +363,23 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
                     }
                     flush();
                 }
-                if (qmin <= qmax) {
+                // prefetch the next item's spectrum range into L2; nothing waits
+                // for it before that item's sample pass (vector loads complete
+                // in order, and the stencil issues none)
+                if (cyc == sg.cy1 && cxc == sg.cx1 && li + 1 < count) {
+                    const int trn = uniform_i(tlist[li + 1]);
+                    const int kn0 = uniform_i(tseg[li + 1].k0), kn1 = uniform_i(tseg[li + 1].k1);
+                    gptr<ST> specn = as_global(
+                        (const ST *)as_const(Fp->spec)[(as_const(Fp->tr) + trn)->slot]);
+                    for (int kk = kn0 + 32 * tid; kk < kn1; kk += 32 * kTableThreads)
+                        touch += (float)spec_at(specn, kk);
+                }
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) {
+                    qmin = min(qmin, __shfl_xor(qmin, o));
+                    qmax = max(qmax, __shfl_xor(qmax, o));
+                }
+                if (lane == 0 && qmin <= qmax) {
                     atomicMin(&sh_qmin, qmin);
                     atomicMax(&sh_qmax, qmax);
                 }
@@ -447,6 +495,7 @@ __global__ __launch_bounds__(kTableThreads, 2) void k_render_table(
                 }
             }
         }
+        if (touch == -1.0f) sh_touch = 1;  // keeps the prefetch loads
         __syncthreads();
 
         // ---- write the tile once
