@@ -150,6 +150,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=120,
                     help="served HIRES-shaped mix; 0 skips it")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrivals per second")
+    ap.add_argument("--profile-once", action="store_true",
+                    help="one batch launch of the timed configuration, then exit (for counters)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="run one device copy of MIB MiB and exit (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -163,6 +167,15 @@ def main():
     from workloads import scene
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_calibration} MiB")
+        return
     log("building c1 workload")
     sc = scene("c1")
     ctx = E.e2e_create(0, 0)
@@ -188,6 +201,14 @@ def main():
         return rr, keep
 
     torch.cuda.synchronize()
+    if args.profile_once:
+        rr, keep = reqs_for(0)
+        E.e2e_render_batch(ctx, rr)
+        torch.cuda.synchronize()
+        log(f"one batch launch of {B} frames done")
+        ld.free()
+        E.e2e_destroy(ctx)
+        return
     log("warmup")
     for w in range(args.warmup):
         rr, keep = reqs_for(w)

@@ -529,14 +529,21 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
     }
     size_t work_n = 0;
     for (int i = 0; i < n; ++i) work_n += tiles[i];
-    size_t scratch_need = seg_total * sizeof(SegDev) + n * sizeof(FrameDev) +
+    size_t tf_total = 0;
+    std::vector<size_t> tf_off(n);
+    for (int i = 0; i < n; ++i) {
+        tf_off[i] = tf_total;
+        tf_total += fs[i]->ntr;
+    }
+    const size_t seg_bytes = seg_total * sizeof(SegDev) + tf_total * sizeof(TraceFrameDev);
+    size_t scratch_need = seg_bytes + n * sizeof(FrameDev) +
                           work_n * sizeof(int2) + nslots_total * sizeof(void *);
     if (ctx->used + temp_bytes + scratch_need > ctx->budget)
         return fail(E2E_ENOMEM, "render needs %zu bytes beyond the %llu-byte budget",
                     temp_bytes + scratch_need, (unsigned long long)ctx->budget);
     e2e_status st;
-    if ((st = grow((void **)&sc->segs, &sc->segs_cap, seg_total * sizeof(SegDev) + 16,
-                   "segs")) != E2E_OK)
+    // planner output: segments of every frame, then the per-trace constants
+    if ((st = grow((void **)&sc->segs, &sc->segs_cap, seg_bytes + 16, "segs")) != E2E_OK)
         return st;
     if ((st = grow((void **)&sc->frames_dev, &sc->frames_cap, n * sizeof(FrameDev),
                    "frames")) != E2E_OK)
@@ -591,6 +598,7 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
         F.tb = P->tb;
         F.sxy = P->sxy;
         F.segs = sc->segs + seg_off[i];
+        F.tf = reinterpret_cast<TraceFrameDev *>(sc->segs + seg_total) + tf_off[i];
         F.beta = r.rv_mps / 299792458.0;
         F.flux_scale = r.flux_scale;
         F.sigma = P->sigma;

@@ -123,6 +123,15 @@ __device__ __forceinline__ double uniform_d(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+template <typename T>
+__device__ __forceinline__ const T *uniform_ptr(const void *p)
+{
+    const unsigned long long b = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(b & 0xffffffffull));
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return (const T *)(((unsigned long long)hi << 32) | lo);
+}
+
 __device__ __forceinline__ int floordiv(int a, int b)
 {
     int q = a / b;

@@ -41,6 +41,15 @@ struct SegDev {
 
 static_assert(sizeof(SegDev) == 16, "SegDev is read as one 16-byte word");
 
+// Per-frame constants of one trace, written by the planner: the affine
+// wavelength map t = t0 + k dt of its samples (Doppler shift included), its
+// flux scale (throughput x exposure) and its spectrum.
+struct TraceFrameDev {
+    double t0, dt, scale;
+    const void *spec;
+};
+static_assert(sizeof(TraceFrameDev) == 32, "TraceFrameDev is 32 bytes");
+
 // Everything one frame's kernels need; lives in device memory.
 struct FrameDev {
     const TraceDev *tr;
@@ -49,6 +58,7 @@ struct FrameDev {
     const double *tb;         // table path: taps [node][s][p][dd]
     const float *sxy;         // separable: [gy][gx][2]
     SegDev *segs;             // [ntx][ntr]
+    TraceFrameDev *tf;        // [ntr]
     double beta, flux_scale;
     double sigma;             // erf
     double gsx, gsy;          // (g-1)/(n-1) node-grid scale

@@ -49,6 +49,14 @@ __global__ void k_plan(const FrameDev *__restrict__ frames, int *__restrict__ er
 
     double t0, dt;
     trace_affine(T, F.beta, &t0, &dt);
+    if (c == 0) {
+        TraceFrameDev tfd;
+        tfd.t0 = t0;
+        tfd.dt = dt;
+        tfd.scale = T.thr * F.flux_scale;
+        tfd.spec = F.spec[T.slot];
+        F.tf[tr] = tfd;
+    }
     int X0 = c * F.tw, X1 = min(X0 + F.tw, F.nx);
     const bool table = F.psf_kind == E2E_PSF_TABLE;
     double hw = table ? (double)F.kw / (2.0 * kOS) : 0.0;

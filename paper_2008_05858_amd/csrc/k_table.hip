@@ -35,6 +35,7 @@ namespace e2e {
 namespace {
 
 constexpr int kNone = 0x3fffffff;  // "no row yet"; far from any real row
+constexpr int kItems = 256;        // trace segments one tile can hold
 
 template <int KW, int DX, int DY, typename ST>
 __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_table(
@@ -68,8 +69,9 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
     __shared__ double bandbuf[BUFF / 2];
     __shared__ double tile[TH][TW];
     __shared__ int kst[NCOL + 1];
-    __shared__ int tlist[kMaxTileTraces];
-    __shared__ SegDev tseg[kMaxTileTraces];
+    __shared__ int tlist[kItems];
+    __shared__ SegDev tseg[kItems];
+    __shared__ TraceFrameDev tmeta[kItems];
     __shared__ int sh_wsum[4], sh_item, sh_qmin, sh_qmax, sh_touch;
 
     float *band = reinterpret_cast<float *>(bandbuf);
@@ -98,7 +100,9 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
         }
         cptr<FrameDev> Fp = as_const(frames) + fi;
         const int ntr = Fp->ntr;
-        const int tx = tile_id % Fp->ntx, ty = tile_id / Fp->ntx;
+        // tiles run down the columns: vertically adjacent tiles share their
+        // traces' spectrum ranges, which then stay in L2
+        const int tx = tile_id / Fp->nty, ty = tile_id % Fp->nty;
         const int X0 = tx * TW, Y0 = ty * TH;
         const SegDev *segs = Fp->segs + (size_t)tx * ntr;
 
@@ -135,21 +139,33 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 if (!((bits >> j) & 1)) continue;
-                if (pos < kMaxTileTraces) {
+                if (pos < kItems) {
                     tlist[pos] = mb + j;
                     tseg[pos] = sgv[j];
+                    tmeta[pos] = Fp->tf[mb + j];
                 } else {
                     atomicOr(err, kErrTileTraces);
                 }
                 ++pos;
             }
-            count = min(count + uniform_i(tot), kMaxTileTraces);
+            count = min(count + uniform_i(tot), kItems);
             __syncthreads();
         }
         for (int e = tid; e < TH * TW; e += kTableThreads) tile[e / TW][e % TW] = 0.0;
         __syncthreads();
+        // Spectrum prefetch, one item ahead: item 0's range now, item i+1's
+        // after item i's sample pass.  Vector loads complete in order, so a
+        // prefetch must follow the loads that are needed before it; the sum
+        // is only consumed at the end of the tile.
+        float touch = 0.0f;
+        auto prefetch = [&](int li) {
+            gptr<ST> sp = as_global(uniform_ptr<ST>(tmeta[li].spec));
+            const int a = uniform_i(tseg[li].k0), b = uniform_i(tseg[li].k1);
+            for (int kk = a + 32 * tid; kk < b; kk += 32 * kTableThreads)
+                touch += (float)spec_at(sp, kk);
+        };
+        if (count > 0) prefetch(0);
 
-        float touch = 0.0f;  // prefetch sink
         for (int li = 0; li < count; ++li) {
             const int tr = uniform_i(tlist[li]);
             SegDev sg;
@@ -172,35 +188,15 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 for (int j = 0; j <= DX; ++j) cxr[j] = Tp->cx[j];
 #pragma unroll
                 for (int j = 0; j <= DY; ++j) cyr[j] = Tp->cy[j];
-                double t0, dt;
-                {
-                    TraceDev Tl;
-                    Tl.lmin = Tp->lmin;
-                    Tl.lmax = Tp->lmax;
-                    Tl.n = Tp->n;
-                    trace_affine(Tl, Fp->beta, &t0, &dt);
-                }
-                // the per-sample polynomial arithmetic reads these from vector
-                // registers: wave-uniform, but the scalar file is needed elsewhere
-#pragma unroll
-                for (int j = 0; j <= DX; ++j) asm volatile("" : "+v"(cxr[j]));
-#pragma unroll
-                for (int j = 0; j <= DY; ++j) asm volatile("" : "+v"(cyr[j]));
-                asm volatile("" : "+v"(t0), "+v"(dt));
-                const double scale = Tp->thr * Fp->flux_scale;
-                gptr<ST> spec = as_global((const ST *)as_const(Fp->spec)[Tp->slot]);
+                const double t0 = uniform_d(tmeta[li].t0), dt = uniform_d(tmeta[li].dt);
+                const double scale = uniform_d(tmeta[li].scale);
+                gptr<ST> spec = as_global(uniform_ptr<ST>(tmeta[li].spec));
                 const double gsx = Fp->gsx, gsy = Fp->gsy;
                 const int gxn = Fp->gx, gyn = Fp->gy;
                 const double ua = fma(horner<DX>(cxr, fma((double)k0, dt, t0)), (double)OS, UC);
                 const double ub = fma(horner<DX>(cxr, fma((double)(k1 - 1), dt, t0)), (double)OS, UC);
                 const double inv_slope = ub > ua ? (double)(k1 - 1 - k0) / (ub - ua) : 0.0;
 
-                // the first item pulls its spectrum into L2 while its column
-                // search runs; later items were prefetched by their predecessor
-                if (li == 0 && cyc == sg.cy0 && cxc == sg.cx0) {
-                    for (int kk = k0 + 32 * tid; kk < k1; kk += 32 * kTableThreads)
-                        touch += (float)spec_at(spec, kk);
-                }
 
                 // ---- 1. samples of each slot column: first k with u(k) >= q
                 const int q = OS * X0 - KW + tid;
@@ -260,6 +256,22 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 int runQy = kNone, rb = kNone;
                 bool run_in = false;
                 int qmin = 0x7fffffff, qmax = -0x7fffffff;
+                // loop-local copies of the wave-uniform constants
+                double cxv[DX + 1], cyv[DY + 1];
+#pragma unroll
+                for (int j = 0; j <= DX; ++j) {
+                    cxv[j] = cxr[j];
+                    
+                }
+#pragma unroll
+                for (int j = 0; j <= DY; ++j) {
+                    cyv[j] = cyr[j];
+                    
+                }
+                double t0v = t0, dtv = dt, scv = scale, gsxv = gsx, gsyv = gsy;
+                
+                double ay0v = ay0, ay1v = ay1, fybv = fyb;
+                
                 auto flush = [&]() {
                     const int o = runQy - rb;
                     if (o < 0 || o > 2) {
@@ -270,7 +282,7 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                         qmin = min(qmin, runQy);
                         qmax = max(qmax, runQy);
                     }
-                    const double fya = fma(ay1, ((double)runQy - UC) / OS, ay0);
+                    const double fya = fma(ay1v, ((double)runQy - UC) / OS, ay0v);
                     // polynomial coefficients (in rho) of cic x node weight
                     double X[2][2][3], Y[2][2][3];
                     auto coef = [](double a, double b, double c[2][2][3]) {
@@ -280,7 +292,7 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                         c[1][0][0] = 0.0;     c[1][0][1] = 1.0 - a;     c[1][0][2] = -b;
                     };
                     coef(fxa, fxb, X);
-                    coef(fya, fyb, Y);
+                    coef(fya, fybv, Y);
                     double Tm[2][2][3];
 #pragma unroll
                     for (int r = 0; r < 2; ++r)
@@ -301,7 +313,7 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                                 double d = fma(X[lr][nx][2], Tm[r][ny][2],
                                                fma(X[lr][nx][1], Tm[r][ny][1],
                                                    X[lr][nx][0] * Tm[r][ny][0]));
-                                dv[r] = (float)(d * scale);
+                                dv[r] = (float)(d * scv);
                             }
                             wr[l][lr][0] += o == 0 ? dv[0] : 0.0f;
                             wr[l][lr][1] += o == 0 ? dv[1] : (o == 1 ? dv[0] : 0.0f);
@@ -310,17 +322,18 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                         }
                 };
                 const double UCq = UC - (double)q;
-                auto sample = [&](int k, double sv) {
-                    double t = fma((double)k, dt, t0);
-                    double x = horner<DX>(cxr, t);
-                    double y = horner<DY>(cyr, t);
+                auto sample = [&](int k, double sv, auto mc) {
+                    double t = fma((double)k, dtv, t0v);
+                    double x = horner<DX>(cxv, t);
+                    double y = horner<DY>(cyv, t);
                     double rx = fma(x, (double)OS, UCq);
                     double vy = fma(y, (double)OS, UC);
                     double fly = floor(vy);
                     int Qy = (int)fly;
                     double ry = vy - fly;
                     bool in = true;
-                    if (multi) in = (ext_cell(x, gsx, gxn) == cxc) & (ext_cell(y, gsy, gyn) == cyc);
+                    if constexpr (decltype(mc)::value)
+                        in = (ext_cell(x, gsxv, gxn) == cxc) & (ext_cell(y, gsyv, gyn) == cyc);
                     double phi = in ? sv : 0.0;
                     if (Qy != runQy) {
                         if (runQy != kNone) {
@@ -346,34 +359,31 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                     m[2][1] = fma(e1, rx2, m[2][1]);
                     m[2][2] = fma(e2, rx2, m[2][2]);
                 };
-                if (ks < ke) {
+                const ST *specv = (const ST *)spec;
+                // a trace segment that stays in one node cell (the usual case)
+                // needs no per-sample cell test: two instances of the loop
+                auto walk = [&](auto mc) {
+                    if (ks >= ke) return;
                     // spectrum values four samples ahead (indices clamped into the
                     // column, so every load is unconditional)
+                    gptr<ST> sp = as_global(specv);
                     const int kl = ke - 1;
-                    ST v0 = spec[min(ks, kl)], v1 = spec[min(ks + 1, kl)];
-                    ST v2 = spec[min(ks + 2, kl)], v3 = spec[min(ks + 3, kl)];
+                    ST v0 = sp[min(ks, kl)], v1 = sp[min(ks + 1, kl)];
+                    ST v2 = sp[min(ks + 2, kl)], v3 = sp[min(ks + 3, kl)];
                     for (int kb = ks; kb < ke; kb += 4) {
-                        const ST n0 = spec[min(kb + 4, kl)], n1 = spec[min(kb + 5, kl)];
-                        const ST n2 = spec[min(kb + 6, kl)], n3 = spec[min(kb + 7, kl)];
-                        sample(kb, (double)v0);
-                        if (kb + 1 < ke) sample(kb + 1, (double)v1);
-                        if (kb + 2 < ke) sample(kb + 2, (double)v2);
-                        if (kb + 3 < ke) sample(kb + 3, (double)v3);
+                        const ST n0 = sp[min(kb + 4, kl)], n1 = sp[min(kb + 5, kl)];
+                        const ST n2 = sp[min(kb + 6, kl)], n3 = sp[min(kb + 7, kl)];
+                        sample(kb, (double)v0, mc);
+                        if (kb + 1 < ke) sample(kb + 1, (double)v1, mc);
+                        if (kb + 2 < ke) sample(kb + 2, (double)v2, mc);
+                        if (kb + 3 < ke) sample(kb + 3, (double)v3, mc);
                         v0 = n0; v1 = n1; v2 = n2; v3 = n3;
                     }
                     flush();
-                }
-                // prefetch the next item's spectrum range into L2; nothing waits
-                // for it before that item's sample pass (vector loads complete
-                // in order, and the stencil issues none)
-                if (cyc == sg.cy1 && cxc == sg.cx1 && li + 1 < count) {
-                    const int trn = uniform_i(tlist[li + 1]);
-                    const int kn0 = uniform_i(tseg[li + 1].k0), kn1 = uniform_i(tseg[li + 1].k1);
-                    gptr<ST> specn = as_global(
-                        (const ST *)as_const(Fp->spec)[(as_const(Fp->tr) + trn)->slot]);
-                    for (int kk = kn0 + 32 * tid; kk < kn1; kk += 32 * kTableThreads)
-                        touch += (float)spec_at(specn, kk);
-                }
+                };
+                if (multi) walk(std::true_type());
+                else walk(std::false_type());
+                if (cyc == sg.cy1 && cxc == sg.cx1 && li + 1 < count) prefetch(li + 1);
 #pragma unroll
                 for (int o = 32; o >= 1; o >>= 1) {
                     qmin = min(qmin, __shfl_xor(qmin, o));

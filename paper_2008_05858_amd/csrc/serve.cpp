@@ -276,7 +276,8 @@ extern "C" e2e_status e2e_serve_submit(e2e_ctx *ctx, const e2e_render_req *req, 
         if (!req->spectra_on_device)
             for (size_t b : q->spec_bytes) fp += b;
         int tw = q->psf->kind == E2E_PSF_TABLE ? table_tw(q->psf->kw) : kSepTile;
-        fp += (uint64_t)((q->fmt->nx + tw - 1) / tw) * q->fmt->ntr * sizeof(SegDev);
+        fp += (uint64_t)((q->fmt->nx + tw - 1) / tw) * q->fmt->ntr * sizeof(SegDev) +
+              (uint64_t)q->fmt->ntr * sizeof(TraceFrameDev);
         q->footprint = fp;
         uint64_t avail = ctx->budget > ctx->used ? ctx->budget - ctx->used : 0;
         if (fp > avail) {

@@ -86,6 +86,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        # One HIP runtime per process: PyTorch ships its own libamdhip64.so.7.
+        # Loading it first makes libe2e.so bind to that copy (same soname);
+        # loading the system copy first would leave torch unable to start HIP.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P = C.POINTER
         L.e2e_create.argtypes = [P(C.c_void_p), C.c_int32, C.c_uint64]
