@@ -49,6 +49,23 @@ def table_flops_per_sample(sc):
     return per_sample + cells * 2 * foot
 
 
+def measured_traffic():
+    """HBM bytes per timed launch from the committed FETCH_SIZE / WRITE_SIZE
+    counter summary (copy-calibrated), or None when render_table's source has
+    changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "render_table_c1_batch4_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_2008_05858_amd", "csrc", "k_table.hip")
+    try:
+        txt = open(path).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", txt, re.S).group(1))
+        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, AttributeError, ValueError):
+        return None
+    return rec["hbm_bytes_per_launch"] if rec.get("kernel_source_sha256") == cur else None
+
+
 def cpu_baseline(sc):
     """The FP64 oracle on one trace of the same workload, single thread."""
     import oracle
@@ -254,8 +271,10 @@ def main():
     bytes_launch = B * (sc.spectrum_bytes() + sc.nx * sc.ny * 4)
     alu = flops_launch / avg_s
     hbm = bytes_launch / avg_s
+    traffic = measured_traffic()
     roof = {"bound": "alu", "achieved": alu / 1e12, "peak": PEAK_ALU / 1e12, "unit": "TFLOP/s",
-            "frac": alu / PEAK_ALU, "traffic": None,
+            "frac": alu / PEAK_ALU, "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": "render_table", "kernel_ms": avg_s * 1e3,
             "algorithmic_flops_per_sample": table_flops_per_sample(sc),
             "hbm_view": {"achieved_GBps": hbm / 1e9, "frac": hbm / PEAK_HBM,
