@@ -517,7 +517,7 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
         int tw, th;
         tile_geom(ps[i], prec, &tw, &th);
         int ntx = (fs[i]->nx + tw - 1) / tw, nty = (fs[i]->ny + th - 1) / th;
-        tiles[i] = ntx * nty;
+        tiles[i] = kind == E2E_PSF_TABLE ? table_units(ntx, nty) : ntx * nty;
         seg_off[i] = seg_total;
         seg_total += (size_t)ntx * fs[i]->ntr;
         spec_off[i] = nslots_total;

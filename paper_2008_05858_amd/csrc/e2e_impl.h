@@ -14,6 +14,7 @@ constexpr int kNCoef = 8;        // polynomial coefficients stored per axis
 constexpr int kOS = 4;           // PSF table cells per pixel on the GPU path
 constexpr int kTableThreads = 256;
 constexpr int kTableTH = 32;     // table-path tile height (rows)
+constexpr int kTableChunk = 8;   // table-path tiles one workgroup walks down a column
 constexpr int kSepTile = 16;     // VALU separable / erf tile edge
 constexpr int kMfmaTW = 64;      // MFMA separable tile width (x)
 constexpr int kMfmaTH = 32;      // MFMA separable tile height (y)
@@ -82,6 +83,8 @@ enum : int {
 
 // Tile geometry of each path.
 inline int table_tw(int kw) { return (kTableThreads - kw) / kOS; }
+// Work units of the table path: runs of kTableChunk tiles down one column.
+inline int table_units(int ntx, int nty) { return ntx * ((nty + kTableChunk - 1) / kTableChunk); }
 
 // Compile-time choices of a render launch (shared by every frame of it).
 struct KernelCfg {

@@ -36,6 +36,7 @@ namespace {
 
 constexpr int kNone = 0x3fffffff;  // "no row yet"; far from any real row
 constexpr int kItems = 256;        // trace segments one tile can hold
+constexpr int kUnf = 64;           // traces one tile can hand on to the next
 
 template <int KW, int DX, int DY, typename ST>
 __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_table(
@@ -53,6 +54,7 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
     static_assert(OS * TW + KW == NCOL, "tile geometry");
     static_assert(TW <= 64, "one wave spans the tile width");
 
+    constexpr int CR = 16;                     // carried rows below a tile
     constexpr int NB = 3;                      // deposit rows per band
     constexpr int NJ = DD + 1;                 // output rows a band reaches
     constexpr int SQ = (NS + 3) / 4;           // slot offsets per wave
@@ -68,6 +70,10 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
     // it, the partial sums of waves 1..3.
     __shared__ double bandbuf[BUFF / 2];
     __shared__ double tile[TH][TW];
+    __shared__ double carry[CR][TW];             // rows of the next tile
+    __shared__ int unf[2][kUnf];                 // traces with rows beyond the carry
+    __shared__ int sh_nunf[2];
+    __shared__ unsigned char tcont[kItems];      // item continues from the tile above
     __shared__ int kst[NCOL + 1];
     __shared__ int tlist[kItems];
     __shared__ SegDev tseg[kItems];
@@ -84,11 +90,11 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
     if (tid == 0) sh_touch = 0;
 
     for (int iter = 0;; ++iter) {
-        int fi, tile_id;
+        int fi, unit;
         if (work == nullptr) {
             if (iter > 0) break;
             fi = 0;
-            tile_id = xcd_remap(blockIdx.x, gridDim.x);
+            unit = xcd_remap(blockIdx.x, gridDim.x);
         } else {
             if (tid == 0) sh_item = atomicAdd(counter, 1);
             __syncthreads();
@@ -96,15 +102,28 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
             if (w >= n_work) break;
             int2 wk = work[w];
             fi = uniform_i(wk.x);
-            tile_id = uniform_i(wk.y);
+            unit = uniform_i(wk.y);
         }
         cptr<FrameDev> Fp = as_const(frames) + fi;
         const int ntr = Fp->ntr;
-        // tiles run down the columns: vertically adjacent tiles share their
-        // traces' spectrum ranges, which then stay in L2
-        const int tx = tile_id / Fp->nty, ty = tile_id % Fp->nty;
-        const int X0 = tx * TW, Y0 = ty * TH;
+        // A unit is a run of kTableChunk tiles down one column, walked top to
+        // bottom.  A trace segment is processed at the first tile of the run
+        // it reaches, for every output row up to CR rows into the next tile
+        // (the carry); only a segment with rows beyond that is taken up again
+        // by the next tile.
+        const int nchunk = (Fp->nty + kTableChunk - 1) / kTableChunk;
+        const int tx = unit / nchunk, ty_a = (unit % nchunk) * kTableChunk;
+        const int ty_b = min(ty_a + kTableChunk, Fp->nty);
+        const int X0 = tx * TW;
         const SegDev *segs = Fp->segs + (size_t)tx * ntr;
+        for (int e = tid; e < CR * TW; e += kTableThreads) carry[e / TW][e % TW] = 0.0;
+        if (tid < 2) sh_nunf[tid] = 0;
+        __syncthreads();
+
+        for (int ty = ty_a; ty < ty_b; ++ty) {
+        const int Y0 = ty * TH;
+        const int up = (ty - ty_a) & 1;  // unfinished list of the tile above
+        const int nup = uniform_i(sh_nunf[up]);
 
         // ---- traces reaching this tile, ascending: each thread tests a run of
         // eight traces (one round of loads), a block-wide prefix sum places them
@@ -113,12 +132,25 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
             const int mb = pb + 8 * tid;
             unsigned bits = 0;
             SegDev sgv[8];
+            unsigned cont = 0;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 sgv[j] = segs[min(mb + j, ntr - 1)];
-                const bool ok = mb + j < ntr && sgv[j].k0 < sgv[j].k1 && sgv[j].ty0 <= ty &&
-                                ty <= sgv[j].ty1;
+                const bool reach = mb + j < ntr && sgv[j].k0 < sgv[j].k1 && sgv[j].ty0 <= ty &&
+                                   ty <= sgv[j].ty1;
+                const bool fresh = sgv[j].ty0 >= ty || ty == ty_a;
+                bool more = nup > kUnf;  // the list overflowed: take every one up
+                if (reach && !fresh && !more) {
+                    int lo = 0, hi = nup;  // unf[up] is ascending
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (unf[up][mid] < mb + j) lo = mid + 1; else hi = mid;
+                    }
+                    more = lo < nup && unf[up][lo] == mb + j;
+                }
+                const bool ok = reach && (fresh || more);
                 bits |= ok ? 1u << j : 0u;
+                cont |= (ok && !fresh) ? 1u << j : 0u;
             }
             const int cnt = __popc(bits);
             int x = cnt;  // inclusive scan over the wave
@@ -143,6 +175,7 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                     tlist[pos] = mb + j;
                     tseg[pos] = sgv[j];
                     tmeta[pos] = Fp->tf[mb + j];
+                    tcont[pos] = (cont >> j) & 1;
                 } else {
                     atomicOr(err, kErrTileTraces);
                 }
@@ -151,8 +184,19 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
             count = min(count + uniform_i(tot), kItems);
             __syncthreads();
         }
-        for (int e = tid; e < TH * TW; e += kTableThreads) tile[e / TW][e % TW] = 0.0;
+        // the tile starts from the rows carried down from the tile above
+        for (int e = tid; e < TH * TW; e += kTableThreads) {
+            const int r = e / TW, c = e % TW;
+            if (r < CR) {
+                tile[r][c] = carry[r][c];
+                carry[r][c] = 0.0;
+            } else {
+                tile[r][c] = 0.0;
+            }
+        }
+        if (tid == 0) sh_nunf[up ^ 1] = 0;
         __syncthreads();
+        const bool last_tile = ty + 1 >= ty_b;
         // Spectrum prefetch, one item ahead: item 0's range now, item i+1's
         // after item i's sample pass.  Vector loads complete in order, so a
         // prefetch must follow the loads that are needed before it; the sum
@@ -179,6 +223,10 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
             }
             const int k0 = sg.k0, k1 = sg.k1;
             const bool multi = (sg.cx0 != sg.cx1) | (sg.cy0 != sg.cy1);
+            // output rows this pass owns: from the tile top (or below the rows
+            // the tile above already carried) to the end of the carry
+            const int out_lo = uniform_i(tcont[li]) ? Y0 + CR : Y0;
+            const int out_hi = last_tile ? Y0 + TH - 1 : Y0 + TH + CR - 1;
 
             for (int cyc = sg.cy0; cyc <= sg.cy1; ++cyc)
             for (int cxc = sg.cx0; cxc <= sg.cx1; ++cxc) {
@@ -401,8 +449,16 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 // A/4 .. A/4 + NJ - 1.
                 const int qlo = uniform_i(sh_qmin), qhi = uniform_i(sh_qmax) + 1;
                 if (qlo > qhi) continue;  // no sample of this cell here (uniform)
-                const int rlo = max(qlo, OS * (Y0 - (DD - 1)));
-                const int rhi = min(qhi, OS * (Y0 + TH) - 1);
+                // rows reaching below this pass: the next tile takes the trace up
+                if (!last_tile && (qhi >> 2) + DD - 1 > out_hi && tid == 0) {
+                    const int n = sh_nunf[up ^ 1];
+                    if (n == 0 || unf[up ^ 1][min(n, kUnf) - 1] != tr) {
+                        if (n < kUnf) unf[up ^ 1][n] = tr;
+                        sh_nunf[up ^ 1] = n + 1;
+                    }
+                }
+                const int rlo = max(qlo, OS * (out_lo - (DD - 1)));
+                const int rhi = min(qhi, OS * out_hi + OS - 1);
                 if (rlo > rhi) continue;
                 for (int A = rlo; A <= rhi; A += NB) {
                     // 3a. the band: right-slot parts of each column's window in its
@@ -491,14 +547,15 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                     }
                     __syncthreads();
                     if (wv == 0 && lane < TW) {
-                        const int n0 = (A >> 2) - Y0;
 #pragma unroll
                         for (int d = 0; d < NJ; ++d) {
-                            const int j = n0 + d;
-                            if (j >= 0 && j < TH)
-                                tile[j][lane] += ((acc[d] + P[d * 64 + lane]) +
-                                                  P[(NJ + d) * 64 + lane]) +
-                                                 P[(2 * NJ + d) * 64 + lane];
+                            const int o = (A >> 2) + d;  // output row
+                            if (o < out_lo || o > out_hi) continue;
+                            const double v = ((acc[d] + P[d * 64 + lane]) +
+                                              P[(NJ + d) * 64 + lane]) +
+                                             P[(2 * NJ + d) * 64 + lane];
+                            if (o < Y0 + TH) tile[o - Y0][lane] += v;
+                            else carry[o - Y0 - TH][lane] += v;
                         }
                     }
                     __syncthreads();
@@ -519,6 +576,7 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
             }
         }
         __syncthreads();
+        }  // tiles of the unit
     }
 }
 
