@@ -35,7 +35,7 @@ namespace e2e {
 namespace {
 
 constexpr int kNone = 0x3fffffff;  // "no row yet"; far from any real row
-constexpr int kItems = 256;        // trace segments one tile can hold
+constexpr int kCand = 256;         // trace segments one run of tiles can hold
 constexpr int kUnf = 64;           // traces one tile can hand on to the next
 
 template <int KW, int DX, int DY, typename ST>
@@ -73,11 +73,12 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
     __shared__ double carry[CR][TW];             // rows of the next tile
     __shared__ int unf[2][kUnf];                 // traces with rows beyond the carry
     __shared__ int sh_nunf[2];
-    __shared__ unsigned char tcont[kItems];      // item continues from the tile above
+    __shared__ unsigned char tcont[kCand];       // item continues from the tile above
     __shared__ int kst[NCOL + 1];
-    __shared__ int tlist[kItems];
-    __shared__ SegDev tseg[kItems];
-    __shared__ TraceFrameDev tmeta[kItems];
+    __shared__ int ctr[kCand];                   // the run's trace segments: trace,
+    __shared__ SegDev cseg[kCand];               // segment record,
+    __shared__ TraceFrameDev cmeta[kCand];       // per-frame constants
+    __shared__ unsigned char tlist[kCand];       // this tile's items (candidate index)
     __shared__ int sh_wsum[4], sh_item, sh_qmin, sh_qmax, sh_touch;
 
     float *band = reinterpret_cast<float *>(bandbuf);
@@ -118,39 +119,21 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
         const SegDev *segs = Fp->segs + (size_t)tx * ntr;
         for (int e = tid; e < CR * TW; e += kTableThreads) carry[e / TW][e % TW] = 0.0;
         if (tid < 2) sh_nunf[tid] = 0;
-        __syncthreads();
 
-        for (int ty = ty_a; ty < ty_b; ++ty) {
-        const int Y0 = ty * TH;
-        const int up = (ty - ty_a) & 1;  // unfinished list of the tile above
-        const int nup = uniform_i(sh_nunf[up]);
-
-        // ---- traces reaching this tile, ascending: each thread tests a run of
-        // eight traces (one round of loads), a block-wide prefix sum places them
-        int count = 0;
+        // ---- the column's trace segments that reach any tile of the run,
+        // ascending: each thread tests a run of eight traces (one round of
+        // loads), a block-wide prefix sum places them
+        int ncand = 0;
         for (int pb = 0; pb < ntr; pb += 8 * NCOL) {
             const int mb = pb + 8 * tid;
             unsigned bits = 0;
             SegDev sgv[8];
-            unsigned cont = 0;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 sgv[j] = segs[min(mb + j, ntr - 1)];
-                const bool reach = mb + j < ntr && sgv[j].k0 < sgv[j].k1 && sgv[j].ty0 <= ty &&
-                                   ty <= sgv[j].ty1;
-                const bool fresh = sgv[j].ty0 >= ty || ty == ty_a;
-                bool more = nup > kUnf;  // the list overflowed: take every one up
-                if (reach && !fresh && !more) {
-                    int lo = 0, hi = nup;  // unf[up] is ascending
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (unf[up][mid] < mb + j) lo = mid + 1; else hi = mid;
-                    }
-                    more = lo < nup && unf[up][lo] == mb + j;
-                }
-                const bool ok = reach && (fresh || more);
+                const bool ok = mb + j < ntr && sgv[j].k0 < sgv[j].k1 && sgv[j].ty0 < ty_b &&
+                                sgv[j].ty1 >= ty_a;
                 bits |= ok ? 1u << j : 0u;
-                cont |= (ok && !fresh) ? 1u << j : 0u;
             }
             const int cnt = __popc(bits);
             int x = cnt;  // inclusive scan over the wave
@@ -161,7 +144,7 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
             }
             if (lane == 63) sh_wsum[wv] = x;
             __syncthreads();
-            int pos = count + x - cnt, tot = 0;
+            int pos = ncand + x - cnt, tot = 0;
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
                 const int v = sh_wsum[w];
@@ -171,18 +154,63 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 if (!((bits >> j) & 1)) continue;
-                if (pos < kItems) {
-                    tlist[pos] = mb + j;
-                    tseg[pos] = sgv[j];
-                    tmeta[pos] = Fp->tf[mb + j];
-                    tcont[pos] = (cont >> j) & 1;
+                if (pos < kCand) {
+                    ctr[pos] = mb + j;
+                    cseg[pos] = sgv[j];
+                    cmeta[pos] = Fp->tf[mb + j];
                 } else {
                     atomicOr(err, kErrTileTraces);
                 }
                 ++pos;
             }
-            count = min(count + uniform_i(tot), kItems);
+            ncand = min(ncand + uniform_i(tot), kCand);
             __syncthreads();
+        }
+
+        for (int ty = ty_a; ty < ty_b; ++ty) {
+        const int Y0 = ty * TH;
+        const int up = (ty - ty_a) & 1;  // unfinished list of the tile above
+        const int nup = uniform_i(sh_nunf[up]);
+
+        // ---- this tile's items, ascending: thread c tests candidate c.  A
+        // segment is taken at the first tile of the run it reaches, and again
+        // only if the tile above listed it as reaching past its carry.
+        int count;
+        {
+            const int c = tid;
+            bool ok = false, cnt_c = false;
+            if (c < ncand) {
+                const SegDev sc = cseg[c];
+                const bool reach = sc.ty0 <= ty && ty <= sc.ty1;
+                const bool fresh = sc.ty0 >= ty || ty == ty_a;
+                bool more = nup > kUnf;  // the list overflowed: take every one up
+                if (reach && !fresh && !more) {
+                    const int t = ctr[c];
+                    int lo = 0, hi = nup;  // unf[up] is ascending
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (unf[up][mid] < t) lo = mid + 1; else hi = mid;
+                    }
+                    more = lo < nup && unf[up][lo] == t;
+                }
+                ok = reach && (fresh || more);
+                cnt_c = ok && !fresh;
+            }
+            const unsigned long long m = __ballot(ok);
+            if (lane == 0) sh_wsum[wv] = __popcll(m);
+            __syncthreads();
+            int pos = __popcll(m & ((1ull << lane) - 1ull)), tot = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const int v = sh_wsum[w];
+                pos += w < wv ? v : 0;
+                tot += v;
+            }
+            if (ok) {
+                tlist[pos] = (unsigned char)c;
+                tcont[pos] = cnt_c;
+            }
+            count = uniform_i(tot);
         }
         // the tile starts from the rows carried down from the tile above
         for (int e = tid; e < TH * TW; e += kTableThreads) {
@@ -203,18 +231,20 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
         // is only consumed at the end of the tile.
         float touch = 0.0f;
         auto prefetch = [&](int li) {
-            gptr<ST> sp = as_global(uniform_ptr<ST>(tmeta[li].spec));
-            const int a = uniform_i(tseg[li].k0), b = uniform_i(tseg[li].k1);
+            const int c = uniform_i(tlist[li]);
+            gptr<ST> sp = as_global(uniform_ptr<ST>(cmeta[c].spec));
+            const int a = uniform_i(cseg[c].k0), b = uniform_i(cseg[c].k1);
             for (int kk = a + 32 * tid; kk < b; kk += 32 * kTableThreads)
                 touch += (float)spec_at(sp, kk);
         };
         if (count > 0) prefetch(0);
 
         for (int li = 0; li < count; ++li) {
-            const int tr = uniform_i(tlist[li]);
+            const int ci = uniform_i(tlist[li]);
+            const int tr = uniform_i(ctr[ci]);
             SegDev sg;
             {
-                int4 raw = *reinterpret_cast<const int4 *>(&tseg[li]);
+                int4 raw = *reinterpret_cast<const int4 *>(&cseg[ci]);
                 raw.x = uniform_i(raw.x);
                 raw.y = uniform_i(raw.y);
                 raw.z = uniform_i(raw.z);
@@ -236,9 +266,9 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 for (int j = 0; j <= DX; ++j) cxr[j] = Tp->cx[j];
 #pragma unroll
                 for (int j = 0; j <= DY; ++j) cyr[j] = Tp->cy[j];
-                const double t0 = uniform_d(tmeta[li].t0), dt = uniform_d(tmeta[li].dt);
-                const double scale = uniform_d(tmeta[li].scale);
-                gptr<ST> spec = as_global(uniform_ptr<ST>(tmeta[li].spec));
+                const double t0 = uniform_d(cmeta[ci].t0), dt = uniform_d(cmeta[ci].dt);
+                const double scale = uniform_d(cmeta[ci].scale);
+                gptr<ST> spec = as_global(uniform_ptr<ST>(cmeta[ci].spec));
                 const double gsx = Fp->gsx, gsy = Fp->gsy;
                 const int gxn = Fp->gx, gyn = Fp->gy;
                 const double ua = fma(horner<DX>(cxr, fma((double)k0, dt, t0)), (double)OS, UC);
