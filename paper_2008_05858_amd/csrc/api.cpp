@@ -244,7 +244,9 @@ extern "C" e2e_status e2e_format_load(e2e_ctx *ctx, const e2e_trace_desc *tr, in
 // Taps of one node: B(vy, vx) = sum of the table over the os x os cells
 // starting at (vx, vy) (cells outside the table are zero), stored as
 // tb[s][p][dd] = B(os dd - p, kw - 1 - s): the taps of one slot offset s are
-// contiguous, which is the order the stencil streams them in.
+// contiguous, which is the order the stencil streams them in.  The sums are
+// exact in FP64; the device copy is rounded once to FP32 (the pixel
+// integrals of the PSF run in FP32, positions in FP64).
 static void node_taps(const float *K, int kw, double *tb)
 {
     const int OS = kOS, NS = kw + OS - 1, DD = (kw + OS - 2) / OS + 1;
@@ -323,14 +325,15 @@ extern "C" e2e_status e2e_psf_load(e2e_ctx *ctx, const e2e_psf_desc *d, e2e_psf_
         return bad(E2E_EINVAL, "unknown PSF kind");
     }
     hipSetDevice(ctx->dev);
-    size_t bytes = tb.size() * sizeof(double) + sxy.size() * sizeof(float);
+    std::vector<float> tbf(tb.begin(), tb.end());
+    size_t bytes = tbf.size() * sizeof(float) + sxy.size() * sizeof(float);
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (ctx->used + bytes > ctx->budget) return bad(E2E_ENOMEM, "tables exceed the HBM budget");
     hipError_t e = hipSuccess;
-    if (!tb.empty()) {
-        e = hipMalloc(&P->tb, tb.size() * sizeof(double));
+    if (!tbf.empty()) {
+        e = hipMalloc(&P->tb, tbf.size() * sizeof(float));
         if (e == hipSuccess)
-            e = hipMemcpy(P->tb, tb.data(), tb.size() * sizeof(double), hipMemcpyHostToDevice);
+            e = hipMemcpy(P->tb, tbf.data(), tbf.size() * sizeof(float), hipMemcpyHostToDevice);
     }
     if (e == hipSuccess && !sxy.empty()) {
         e = hipMalloc(&P->sxy, sxy.size() * sizeof(float));

@@ -29,7 +29,7 @@ struct PsfRes {
     int kind = 0;
     double sigma = 0;
     int H = 0, gx = 1, gy = 1, kw = 0, kh = 0, os = 0;
-    double *tb = nullptr;   // table taps
+    float *tb = nullptr;    // table taps (FP32)
     float *sxy = nullptr;   // separable sigma grid
     size_t bytes = 0;
     int refs = 0;

@@ -56,7 +56,7 @@ struct FrameDev {
     const TraceDev *tr;
     const void *const *spec;  // device array of device pointers, per slot
     void *out;
-    const double *tb;         // table path: taps [node][s][p][dd]
+    const float *tb;          // table path: FP32 taps [node][s][p][dd]
     const float *sxy;         // separable: [gy][gx][2]
     SegDev *segs;             // [ntx][ntr]
     TraceFrameDev *tf;        // [ntr]

@@ -22,9 +22,9 @@
 //      private 4-row deposit window held in registers;
 //   3. for each band of 3 deposit rows that holds data, lays the windows out
 //      as a dense band in LDS, and each wave applies the node stencils of a
-//      quarter of the slot offsets (taps streamed through the scalar cache,
-//      FP64 sums); the four wave partials are added into the FP64 LDS tile in
-//      a fixed order.
+//      quarter of the slot offsets (FP32 taps streamed through the scalar
+//      cache, FP32 sums per node layer added into FP64); the four wave
+//      partials are added into the FP64 LDS tile in a fixed order.
 // The summation order is fixed, so reruns are bitwise identical.
 #include <type_traits>
 
@@ -526,21 +526,24 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
 #pragma unroll
                     for (int d = 0; d < NJ; ++d) acc[d] = 0.0;
                     const int s0 = wv * SQ;
-                    cptr<double> tbase = as_const(Fp->tb) + (size_t)s0 * OS * DD;
+                    cptr<float> tbase = as_const(Fp->tb) + (size_t)s0 * OS * DD;
                     auto stencil = [&](auto cph) {
                         constexpr int C = decltype(cph)::value;
 #pragma unroll 1
                         for (int L = 0; L < 4; ++L) {
                             const int mx = min(nbx + (L & 1), gxn - 1);
                             const int my = min(nby + (L >> 1), gyn - 1);
-                            cptr<double> taps = tbase + (size_t)(my * gxn + mx) * NODE;
+                            cptr<float> taps = tbase + (size_t)(my * gxn + mx) * NODE;
+                            float a32[NJ];
+#pragma unroll
+                            for (int d = 0; d < NJ; ++d) a32[d] = 0.0f;
 #pragma unroll 1
                             for (int ss = 0; ss < SQ; ++ss) {
                                 const int sl = s0 + ss;
                                 if (sl >= NS) break;  // uniform
                                 const int a = (sl & 3) * PQ + clane + (sl >> 2);
                                 float dv[NB];
-                                double tv[NB][DD];
+                                float tv[NB][DD];
 #pragma unroll
                                 for (int r = 0; r < NB; ++r) {
                                     dv[r] = band[(L * NB + r) * PR + a];
@@ -552,14 +555,15 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
 #pragma unroll
                                 for (int r = 0; r < NB; ++r) {
                                     const int p = (C + r) & 3, n = (C + r) >> 2;
-                                    const double d = (double)dv[r];
 #pragma unroll
                                     for (int dd = 0; dd < DD; ++dd) {
                                         if (p == 0 && dd == DD - 1) continue;  // zero tap row
-                                        acc[n + dd] = fma(d, tv[r][dd], acc[n + dd]);
+                                        a32[n + dd] = fmaf(dv[r], tv[r][dd], a32[n + dd]);
                                     }
                                 }
                             }
+#pragma unroll
+                            for (int d = 0; d < NJ; ++d) acc[d] += (double)a32[d];
                         }
                     };
                     switch (A & 3) {

@@ -113,7 +113,7 @@ def test_serve_admission_by_footprint():
     gu = _gu()
     sc = scene("mini_table")
     ntx = -(-sc.nx // 56)
-    tables = sc.psf.gx * sc.psf.gy * 4 * 35 * 9 * 8 + len(sc.traces) * 176
+    tables = sc.psf.gx * sc.psf.gy * 4 * 35 * 9 * 4 + len(sc.traces) * 176  # FP32 taps
     footprint = sc.nx * sc.ny * 4 + ntx * len(sc.traces) * 16
     ctx = E.e2e_create(0, tables + int(1.5 * footprint))
     ld = P.Loaded(ctx, sc)
