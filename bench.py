@@ -232,6 +232,17 @@ def main():
         E.e2e_render_batch(ctx, rr)
     torch.cuda.synchronize()
 
+    # launch autotuning on the timed configuration (not timed); the plain
+    # renderer below uses the same work-unit length
+    rr, keep = reqs_for(0)
+    tune = E.e2e_autotune(ctx, rr)
+    tune_rec = {"chunk_tiles": tune.chunk, "workgroups_per_cu": tune.resident,
+                "ms_per_launch": tune.ms,
+                "candidates": [[tune.cand_chunk[i], tune.cand_resident[i], round(tune.cand_ms[i], 4)]
+                               for i in range(tune.n_candidates)]}
+    log(f"autotune: chunk {tune.chunk} tiles, {tune.resident} workgroups/CU, {tune.ms:.3f} ms")
+    torch.cuda.synchronize()
+
     # timed region: K steps, kernel events on the launch stream
     E.e2e_reset_kernel_time(ctx)
     E.e2e_set_profiling(ctx, True)
@@ -291,6 +302,7 @@ def main():
            "latency_ms_p50": float(np.percentile(lat, 50)),
            "latency_ms_p99": float(np.percentile(lat, 99)),
            "plan_ms_per_launch": ms_plan / max(n_plan, 1),
+           "autotune": tune_rec,
            "roofline": roof}
     if args.serve_requests > 0:
         res["serve"] = serve_bench(E, P, torch, ctx, sc, ld, specs, args.serve_requests,

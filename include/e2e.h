@@ -216,6 +216,32 @@ e2e_status e2e_serve_poll(e2e_ctx *ctx, e2e_ticket t, int32_t timeout_ms,
 e2e_status e2e_serve_stop(e2e_ctx *ctx);
 
 /*
+ * Launch autotuner (the batch / serve orchestration of Sec. 3, sized to one
+ * GPU).  Renders the given requests (n = 1: the plain renderer; n > 1: one
+ * persistent batch launch) under each candidate launch choice -- work-unit
+ * length in tiles (table path: 2, 4, 8, 16) and, for batches, persistent
+ * workgroups per CU (1..3) -- times them with HIP events (a warm-up run,
+ * then the best of two), and keeps the fastest for the requests' workload
+ * shapes (PSF kind and grid, precision, spectrum type, detector size, trace
+ * count and degrees).  Later e2e_render, e2e_render_batch and served
+ * requests of those shapes use it.  The requests' outputs are written by
+ * the runs.  The unit length changes only the fixed order in which a
+ * pixel's contributions are summed (results stay deterministic per choice,
+ * within rounding of each other); the grid width does not change results.
+ * Errors: those of e2e_render_batch; E2E_EINVAL for n < 1 or NULL reqs.
+ */
+#define E2E_TUNE_MAX 16
+typedef struct {
+    int32_t chunk, resident;      /* the choice kept                           */
+    double ms;                    /* its time per launch                       */
+    int32_t n_candidates;
+    int32_t cand_chunk[E2E_TUNE_MAX], cand_resident[E2E_TUNE_MAX];
+    double cand_ms[E2E_TUNE_MAX];
+} e2e_tune_report;
+e2e_status e2e_autotune(e2e_ctx *ctx, const e2e_render_req *reqs, int32_t n,
+                        e2e_tune_report *report);
+
+/*
  * Photon noise on an existing expected-count frame, in place (Sec. 2.2):
  * frame[p] <- Poisson(frame[p]) with the counter stream of pixel p.
  */

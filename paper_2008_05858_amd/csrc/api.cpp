@@ -510,6 +510,14 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
     cfg.kw = kind == E2E_PSF_TABLE ? ps[0]->kw : (kind == E2E_PSF_SEPARABLE ? 1 : 0);
     cfg.spec_f64 = reqs[0].spectrum_dtype == E2E_F64;
     cfg.precision = prec;
+    // launch choices of each frame's workload shape (e2e_autotune), else
+    // defaults (ctx->mu is held for the whole call)
+    std::vector<TuneRec> tr(n);
+    for (int i = 0; i < n; ++i) {
+        auto it = ctx->tune.find(tune_key(fs[i], ps[i], prec, reqs[i].spectrum_dtype));
+        if (it != ctx->tune.end()) tr[i] = it->second;
+    }
+    cfg.resident = tr[0].resident;
     size_t seg_total = 0;
     std::vector<size_t> seg_off(n);
     std::vector<int> tiles(n);
@@ -520,7 +528,7 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
         int tw, th;
         tile_geom(ps[i], prec, &tw, &th);
         int ntx = (fs[i]->nx + tw - 1) / tw, nty = (fs[i]->ny + th - 1) / th;
-        tiles[i] = kind == E2E_PSF_TABLE ? table_units(ntx, nty) : ntx * nty;
+        tiles[i] = kind == E2E_PSF_TABLE ? table_units(ntx, nty, tr[i].chunk) : ntx * nty;
         seg_off[i] = seg_total;
         seg_total += (size_t)ntx * fs[i]->ntr;
         spec_off[i] = nslots_total;
@@ -622,6 +630,7 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
         F.th = th;
         F.ntx = (fm->nx + tw - 1) / tw;
         F.nty = (fm->ny + th - 1) / th;
+        F.chunk = tr[i].chunk;
         F.poisson = r.poisson ? 1 : 0;
         F.frame_index = r.frame_index;
         F.seed = r.seed;
@@ -716,8 +725,8 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
             maxpix = std::max(maxpix, (int64_t)sc->h_frames[i].nx * sc->h_frames[i].ny);
         }
         char key[256];
-        snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%zu/%d/%lld/%d/%p/%p", kind, cfg.kw,
-                 cfg.degx, cfg.degy, cfg.spec_f64, prec, n, work_n, maxw,
+        snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%zu/%d/%lld/%d/%p/%p", kind, cfg.kw,
+                 cfg.resident, cfg.degx, cfg.degy, cfg.spec_f64, prec, n, work_n, maxw,
                  any_noise ? (long long)maxpix : 0ll, (int)any_noise, (void *)sc->frames_dev,
                  (void *)sc->work);
         auto it = sc->graphs.find(key);
@@ -773,6 +782,112 @@ e2e_status e2e::check_err_word(int w)
 extern "C" e2e_status e2e_render(e2e_ctx *ctx, const e2e_render_req *req)
 {
     return run_frames(ctx, req, 1, false, nullptr);
+}
+
+std::string e2e::tune_key(const FormatRes *f, const PsfRes *p, int precision, int spectrum_dtype)
+{
+    char k[160];
+    snprintf(k, sizeof k, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%d", p->kind, p->kw, p->gx, p->gy, precision,
+             spectrum_dtype, f->nx, f->ny, f->ntr, f->degx * 16 + f->degy);
+    return k;
+}
+
+// Candidate launch choices are rendered on the caller's own requests (a warm
+// run, then the best of two timed runs) and the fastest is kept for their
+// workload shapes.  The work-unit length changes only the order in which a
+// pixel's contributions are summed (the result stays deterministic for a
+// given choice); the persistent-grid width changes nothing in the result.
+extern "C" e2e_status e2e_autotune(e2e_ctx *ctx, const e2e_render_req *reqs, int32_t n,
+                                   e2e_tune_report *report)
+{
+    if (!ctx || !reqs || n < 1) return fail(E2E_EINVAL, "e2e_autotune: bad arguments");
+    std::vector<std::string> keys(n);
+    bool table = false;
+    {
+        // handles are looked up under the context lock; run_frames takes it
+        // again for each timed run, so it is not held across them
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (int i = 0; i < n; ++i) {
+            FormatRes *f = nullptr;
+            PsfRes *p = nullptr;
+            e2e_status st = validate_req(ctx, &reqs[i], &f, &p);
+            if (st != E2E_OK) return st;
+            keys[i] = tune_key(f, p, reqs[i].precision, reqs[i].spectrum_dtype);
+            if (i == 0) table = p->kind == E2E_PSF_TABLE;
+        }
+    }
+    const bool batch = n > 1;
+    std::vector<int> chunks = table ? std::vector<int>{2, 4, 8, 16} : std::vector<int>{kTableChunk};
+    // a single-frame tuning keeps the batch width already chosen for the shape
+    int keep_resident = 0;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->tune.find(keys[0]);
+        if (it != ctx->tune.end()) keep_resident = it->second.resident;
+    }
+    std::vector<int> residents =
+        batch ? std::vector<int>{1, 2, 3} : std::vector<int>{keep_resident};
+    hipSetDevice(ctx->dev);
+    hipStream_t s = reqs[0].hip_stream ? (hipStream_t)reqs[0].hip_stream : ctx->stream;
+    hipEvent_t e0, e1;
+    hipError_t he;
+    if ((he = hipEventCreate(&e0)) != hipSuccess) return hip_fail(he, "event");
+    if ((he = hipEventCreate(&e1)) != hipSuccess) {
+        hipEventDestroy(e0);
+        return hip_fail(he, "event");
+    }
+    // synchronous runs for timing, whatever the requests' flags say
+    std::vector<e2e_render_req> rq(reqs, reqs + n);
+    for (auto &r : rq) r.flags &= ~(uint32_t)E2E_FLAG_ASYNC;
+    e2e_tune_report rep{};
+    double best = 1e300;
+    TuneRec best_rec;
+    e2e_status st = E2E_OK;
+    for (int c : chunks) {
+        for (int r : residents) {
+            TuneRec t;
+            t.chunk = c;
+            t.resident = r;
+            {
+                std::lock_guard<std::mutex> lk(ctx->mu);
+                for (auto &k : keys) ctx->tune[k] = t;
+            }
+            double ms = 1e300;
+            for (int rep_i = 0; rep_i < 3 && st == E2E_OK; ++rep_i) {
+                hipEventRecord(e0, s);
+                st = run_frames(ctx, rq.data(), n, batch, nullptr);
+                hipEventRecord(e1, s);
+                hipEventSynchronize(e1);
+                float f = 0.f;
+                hipEventElapsedTime(&f, e0, e1);
+                if (rep_i > 0) ms = std::min(ms, (double)f);  // first run warms up
+            }
+            if (st != E2E_OK) break;
+            if (rep.n_candidates < E2E_TUNE_MAX) {
+                rep.cand_chunk[rep.n_candidates] = c;
+                rep.cand_resident[rep.n_candidates] = r;
+                rep.cand_ms[rep.n_candidates] = ms;
+                rep.n_candidates++;
+            }
+            if (ms < best) {
+                best = ms;
+                best_rec = t;
+            }
+        }
+        if (st != E2E_OK) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (auto &k : keys) ctx->tune[k] = best_rec;
+    }
+    if (st != E2E_OK) return st;
+    rep.chunk = best_rec.chunk;
+    rep.resident = best_rec.resident;
+    rep.ms = best;
+    if (report) *report = rep;
+    return E2E_OK;
 }
 
 extern "C" e2e_status e2e_render_batch(e2e_ctx *ctx, const e2e_render_req *reqs, int32_t n)

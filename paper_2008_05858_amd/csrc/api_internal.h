@@ -74,6 +74,14 @@ struct Server;
 
 }  // namespace e2e
 
+namespace e2e {
+// Launch choices of one workload shape, set by e2e_autotune.
+struct TuneRec {
+    int chunk = kTableChunk;  // table path: tiles per work unit
+    int resident = 0;         // persistent launches: workgroups per CU (0 = default)
+};
+}  // namespace e2e
+
 struct e2e_ctx {
     int dev = 0;
     uint64_t budget = 0;
@@ -90,6 +98,7 @@ struct e2e_ctx {
     std::map<std::string, std::pair<int64_t, double>> prof_acc;
     std::chrono::steady_clock::time_point t0;
     e2e::Server *srv = nullptr;  // owned by serve.cpp
+    std::map<std::string, e2e::TuneRec> tune;  // by workload shape (guarded by mu)
     std::mutex srv_mu;
 };
 
@@ -104,6 +113,7 @@ e2e_status validate_req(e2e_ctx *ctx, const e2e_render_req *r, FormatRes **pf, P
 e2e_status run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool batch,
                       int *unused);
 e2e_status check_err_word(int w);
+std::string tune_key(const FormatRes *f, const PsfRes *p, int precision, int spectrum_dtype);
 void prof_begin(e2e_ctx *ctx, hipStream_t s, const char *name);
 void prof_end(e2e_ctx *ctx, hipStream_t s);
 void serve_shutdown(e2e_ctx *ctx);

@@ -14,7 +14,7 @@ constexpr int kNCoef = 8;        // polynomial coefficients stored per axis
 constexpr int kOS = 4;           // PSF table cells per pixel on the GPU path
 constexpr int kTableThreads = 256;
 constexpr int kTableTH = 32;     // table-path tile height (rows)
-constexpr int kTableChunk = 8;   // table-path tiles one workgroup walks down a column
+constexpr int kTableChunk = 8;   // default run of table-path tiles one workgroup walks
 constexpr int kSepTile = 16;     // VALU separable / erf tile edge
 constexpr int kMfmaTW = 64;      // MFMA separable tile width (x)
 constexpr int kMfmaTH = 32;      // MFMA separable tile height (y)
@@ -68,6 +68,7 @@ struct FrameDev {
     int32_t spec_f64, out_f64;
     int32_t precision;
     int32_t tw, th, ntx, nty;
+    int32_t chunk;            // table path: tiles per work unit
     int32_t poisson;
     uint32_t frame_index;
     uint64_t seed;
@@ -83,8 +84,8 @@ enum : int {
 
 // Tile geometry of each path.
 inline int table_tw(int kw) { return (kTableThreads - kw) / kOS; }
-// Work units of the table path: runs of kTableChunk tiles down one column.
-inline int table_units(int ntx, int nty) { return ntx * ((nty + kTableChunk - 1) / kTableChunk); }
+// Work units of the table path: runs of `chunk` tiles down one column.
+inline int table_units(int ntx, int nty, int chunk) { return ntx * ((nty + chunk - 1) / chunk); }
 
 // Compile-time choices of a render launch (shared by every frame of it).
 struct KernelCfg {
@@ -94,6 +95,7 @@ struct KernelCfg {
     int plain_tiles;    // plain launch: tiles of frame 0 (one block each)
     int precision;      // E2E_PREC_*
     int mfma_tiles;     // separable MFMA path: tiles of frame 0
+    int resident;       // persistent launches: workgroups per CU (0 = path default)
 };
 
 // Launch wrappers (each .hip file owns its kernels).  work == nullptr

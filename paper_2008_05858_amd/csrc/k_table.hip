@@ -107,14 +107,15 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
         }
         cptr<FrameDev> Fp = as_const(frames) + fi;
         const int ntr = Fp->ntr;
-        // A unit is a run of kTableChunk tiles down one column, walked top to
+        // A unit is a run of `chunk` tiles down one column, walked top to
         // bottom.  A trace segment is processed at the first tile of the run
         // it reaches, for every output row up to CR rows into the next tile
         // (the carry); only a segment with rows beyond that is taken up again
         // by the next tile.
-        const int nchunk = (Fp->nty + kTableChunk - 1) / kTableChunk;
-        const int tx = unit / nchunk, ty_a = (unit % nchunk) * kTableChunk;
-        const int ty_b = min(ty_a + kTableChunk, Fp->nty);
+        const int chunk = Fp->chunk;
+        const int nchunk = (Fp->nty + chunk - 1) / chunk;
+        const int tx = unit / nchunk, ty_a = (unit % nchunk) * chunk;
+        const int ty_b = min(ty_a + chunk, Fp->nty);
         const int X0 = tx * TW;
         const SegDev *segs = Fp->segs + (size_t)tx * ntr;
         for (int e = tid; e < CR * TW; e += kTableThreads) carry[e / TW][e % TW] = 0.0;
@@ -642,7 +643,8 @@ hipError_t launch_deg(const FrameDev *frames_dev, int degx, int degy, int spec_f
 hipError_t launch_table(const FrameDev *frames_dev, const KernelCfg &cfg, const int2 *work,
                         int n_work, int *counter, int *err, hipStream_t s)
 {
-    const int resident = cfg.kw <= 32 ? 3 : 2;  // workgroups per CU
+    const int fit = cfg.kw <= 32 ? 3 : 2;  // workgroups per CU the kernel's resources allow
+    const int resident = cfg.resident > 0 && cfg.resident < fit ? cfg.resident : fit;
     const int cap = 256 * resident;
     int nblocks = work == nullptr ? cfg.plain_tiles : (n_work < cap ? n_work : cap);
     if (nblocks <= 0) return hipSuccess;

@@ -30,7 +30,8 @@ EXPORTS = ["e2e_create", "e2e_destroy", "e2e_last_error", "e2e_version", "e2e_fo
            "e2e_psf_load", "e2e_format_free", "e2e_psf_free", "e2e_render", "e2e_render_batch",
            "e2e_serve_start", "e2e_serve_submit", "e2e_serve_poll", "e2e_serve_stop",
            "e2e_noise_poisson", "e2e_philox_blocks", "e2e_set_profiling", "e2e_kernel_time",
-           "e2e_reset_kernel_time"]
+           "e2e_reset_kernel_time", "e2e_autotune"]
+E2E_TUNE_MAX = 16
 
 
 class e2e_trace_desc(C.Structure):
@@ -56,6 +57,14 @@ class e2e_render_req(C.Structure):
                 ("poisson", C.c_int32), ("precision", C.c_int32), ("out", C.c_void_p),
                 ("out_dtype", C.c_int32), ("out_on_device", C.c_int32),
                 ("hip_stream", C.c_void_p), ("flags", C.c_uint32)]
+
+
+class e2e_tune_report(C.Structure):
+    _fields_ = [("chunk", C.c_int32), ("resident", C.c_int32), ("ms", C.c_double),
+                ("n_candidates", C.c_int32),
+                ("cand_chunk", C.c_int32 * E2E_TUNE_MAX),
+                ("cand_resident", C.c_int32 * E2E_TUNE_MAX),
+                ("cand_ms", C.c_double * E2E_TUNE_MAX)]
 
 
 class e2e_render_stats(C.Structure):
@@ -118,6 +127,7 @@ def lib():
         L.e2e_set_profiling.argtypes = [C.c_void_p, C.c_int32]
         L.e2e_kernel_time.argtypes = [C.c_void_p, C.c_char_p, P(C.c_int64), P(C.c_double)]
         L.e2e_reset_kernel_time.argtypes = [C.c_void_p]
+        L.e2e_autotune.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, P(e2e_tune_report)]
         for n in EXPORTS:
             if n not in ("e2e_destroy", "e2e_last_error", "e2e_version"):
                 getattr(L, n).restype = C.c_int32
@@ -215,6 +225,15 @@ def e2e_philox_blocks(ctx, seed, frame_index, pixel0, n_pixels, blocks):
 
 def e2e_set_profiling(ctx, on):
     return check(lib().e2e_set_profiling(ctx, 1 if on else 0))
+
+
+def e2e_autotune(ctx, reqs):
+    """Time the candidate launch choices on `reqs` and keep the fastest for
+    their workload shapes; returns the e2e_tune_report."""
+    arr = (e2e_render_req * len(reqs))(*reqs)
+    rep = e2e_tune_report()
+    check(lib().e2e_autotune(ctx, arr, len(reqs), C.byref(rep)))
+    return rep
 
 
 def e2e_kernel_time(ctx, name):

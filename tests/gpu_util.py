@@ -56,9 +56,9 @@ def render(scene, req=None, loaded=None, out_dtype=None, context=None, **kw):
     return res
 
 
-def render_batch(scenes, reqs, loadeds):
+def render_batch(scenes, reqs, loadeds, context=None):
     import torch
-    c = ctx()
+    c = context if context is not None else ctx()
     outs, rr, keeps = [], [], []
     for sc, rq, ld in zip(scenes, reqs, loadeds):
         specs, sdt = device_spectra(sc)
