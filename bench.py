@@ -156,6 +156,73 @@ def serve_bench(E, P, torch, ctx, c1, ld1, specs1, n_req, rate, log):
                                    for k, v in lat.items() if v}}
 
 
+def secondary(E, P, torch, ctx, sc1, ld1, specs1, log):
+    """Measurements of the other rows of the path, beside the headline:
+    separable PSF (VALU FP64/FP32 and MFMA fp16/bf16 hi/lo) on the C2 frame,
+    Poisson noise on the C1 frame (HBM-bound: read + write the frame), and a
+    HIRES-shaped C4 frame on the table path.  Kernel times are HIP-event
+    averages over `reps` launches after one warm-up."""
+    from workloads import scene
+    res = {}
+    reps = 3
+
+    def kernel_ms(render, name):
+        render()
+        torch.cuda.synchronize()
+        E.e2e_reset_kernel_time(ctx)
+        E.e2e_set_profiling(ctx, True)
+        for _ in range(reps):
+            render()
+        E.e2e_set_profiling(ctx, False)
+        n, ms = E.e2e_kernel_time(ctx, name)
+        return ms / max(n, 1)
+
+    log("secondary: c2 separable precision variants")
+    c2 = scene("c2")
+    ld2 = P.Loaded(ctx, c2)
+    sp2 = [torch.from_numpy(s).to("cuda") for s in c2.spectra]
+    out2 = torch.empty((c2.ny, c2.nx), dtype=torch.float32, device="cuda")
+    upd2 = c2.updates()
+    sep = {}
+    for prec, kname in (("f64", "render_sep"), ("f32", "render_sep"),
+                        ("f16_hilo", "render_sep_mfma"), ("bf16_hilo", "render_sep_mfma")):
+        r, k = P.make_req(ld2, [s.data_ptr() for s in sp2], E.E2E_F32, out2.data_ptr(),
+                          E.E2E_F32, spectra_on_device=True, out_on_device=True, rv_mps=2.0,
+                          precision=prec)
+        ms = kernel_ms(lambda: E.e2e_render(ctx, r), kname)
+        sep[prec] = {"kernel": kname, "kernel_ms": ms, "updates_per_s": upd2 / (ms / 1e3),
+                     "frames_per_s": 1e3 / ms}
+    res["c2_separable"] = {"updates_per_frame": upd2, "footprint_px": (2 * c2.psf.half_width + 1) ** 2,
+                           "by_precision": sep}
+    ld2.free()
+    del sp2, out2
+
+    log("secondary: poisson noise on the c1 frame")
+    out1 = torch.empty((sc1.ny, sc1.nx), dtype=torch.float32, device="cuda")
+    r, k = P.make_req(ld1, [s.data_ptr() for s in specs1], E.E2E_F32, out1.data_ptr(),
+                      E.E2E_F32, spectra_on_device=True, out_on_device=True, rv_mps=1.0,
+                      poisson=True, seed=7)
+    ms = kernel_ms(lambda: E.e2e_render(ctx, r), "noise")
+    nbytes = 2 * sc1.nx * sc1.ny * 4
+    res["noise_c1"] = {"kernel_ms": ms, "bytes_per_launch": nbytes,
+                       "achieved_GBps": nbytes / (ms / 1e3) / 1e9,
+                       "hbm_frac": nbytes / (ms / 1e3) / PEAK_HBM}
+    del out1
+
+    log("secondary: c4 HIRES-shaped frame")
+    c4 = scene("c4")
+    ld4 = P.Loaded(ctx, c4)
+    sp4 = [torch.from_numpy(s).to("cuda") for s in c4.spectra]
+    out4 = torch.empty((c4.ny, c4.nx), dtype=torch.float32, device="cuda")
+    r, k = P.make_req(ld4, [s.data_ptr() for s in sp4], E.E2E_F32, out4.data_ptr(),
+                      E.E2E_F32, spectra_on_device=True, out_on_device=True, rv_mps=-1.0)
+    ms = kernel_ms(lambda: E.e2e_render(ctx, r), "render_table")
+    res["c4_table"] = {"kernel_ms": ms, "updates_per_s": c4.updates() / (ms / 1e3),
+                       "frames_per_s": 1e3 / ms, "samples": c4.n_samples}
+    ld4.free()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +234,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=120,
                     help="served HIRES-shaped mix; 0 skips it")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrivals per second")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the separable / noise / HIRES-shaped measurements")
     ap.add_argument("--profile-once", action="store_true",
                     help="one batch launch of the timed configuration, then exit (for counters)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -304,6 +373,8 @@ def main():
            "plan_ms_per_launch": ms_plan / max(n_plan, 1),
            "autotune": tune_rec,
            "roofline": roof}
+    if not args.no_secondary:
+        res["secondary"] = secondary(E, P, torch, ctx, sc, ld, specs, log)
     if args.serve_requests > 0:
         res["serve"] = serve_bench(E, P, torch, ctx, sc, ld, specs, args.serve_requests,
                                    args.serve_rate, log)
