@@ -60,6 +60,11 @@ def lib():
         L.orc_philox_blocks.restype = None
         L.orc_poisson_frame.argtypes = [dp, C.c_int64, C.c_uint64, C.c_uint32, dp]
         L.orc_poisson_frame.restype = None
+        u16p = C.POINTER(C.c_uint16)
+        L.orc_detector.argtypes = [dp, dp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                   C.c_double, C.c_double, C.c_int, dp, C.c_double, C.c_double,
+                                   C.c_double, C.c_int, C.c_uint64, C.c_uint32, u16p, dp]
+        L.orc_detector.restype = None
         _lib = L
     return _lib
 
@@ -192,3 +197,25 @@ def poisson_frame(mean, seed, frame):
     lib().orc_poisson_frame(_ptr(m, C.c_double), m.size, seed, frame,
                             _ptr(out, C.c_double))
     return out
+
+
+def detector(F, *, prnu=None, exposure_s=1.0, dark_e_per_s=0.0, shot_noise=True,
+             xtalk=None, ron_e=0.0, gain=1.0, bias=0.0, bits=16, seed=0, frame=0,
+             window=None, want_r=False):
+    """Detector stage (Sec. 2.2) of an expected-count frame F [ny][nx] (FP64
+    oracle): returns uint16 ADU of `window` = (x0, y0, w, h) (default: the
+    whole frame), and R (electrons before quantisation) if want_r."""
+    F = np.ascontiguousarray(F, np.float64)
+    ny, nx = F.shape
+    x0, y0, w, h = window if window is not None else (0, 0, nx, ny)
+    G = None if prnu is None else np.ascontiguousarray(prnu, np.float64)
+    K = np.ascontiguousarray(np.eye(1, 9, 4).reshape(9) if xtalk is None else
+                             np.asarray(xtalk, np.float64).reshape(9))
+    adu = np.zeros((h, w), np.uint16)
+    r = np.zeros((h, w), np.float64) if want_r else None
+    lib().orc_detector(_ptr(F, C.c_double), _ptr(G, C.c_double) if G is not None else None,
+                       nx, ny, x0, y0, w, h, float(exposure_s), float(dark_e_per_s),
+                       1 if shot_noise else 0, _ptr(K, C.c_double), float(ron_e), float(gain),
+                       float(bias), int(bits), int(seed), int(frame), _ptr(adu, C.c_uint16),
+                       _ptr(r, C.c_double) if want_r else None)
+    return (adu, r) if want_r else adu

@@ -458,3 +458,83 @@ void orc_poisson_frame(const double *mean, int64_t n, uint64_t seed,
         out[p] = poisson_draw(mean[p], &st);
     }
 }
+
+/* ---------------------------------------------------------- detector stage */
+
+/*
+ * The detector stage that Sec. 2.2 applies to the final echellogram (photon
+ * noise, dark current, read-out noise, pixel response non-uniformity,
+ * cross-talk), in this order per pixel p = j nx + i:
+ *   mu = G[p] F[p] + dark t          (PRNU gain map G, 1 if absent)
+ *   N  = Poisson(mu) (stream blocks 0, 1, ...) or mu without shot noise
+ *   E  = sum over dy, dx in -1..1 (dy outer) of K[dy+1][dx+1] N[p - (dx, dy)],
+ *        FP64 fma in that order, pixels off the detector contributing 0
+ *        (charge leaking off the chip is lost)
+ *   R  = E + ron Z, Z = sqrt(-2 ln u1) cos(2 pi u2) (Box-Muller) from
+ *        Philox block 2^31 of the pixel's stream: u1 from its words 0-1,
+ *        u2 from words 2-3 (a counter range the Poisson draws never reach)
+ *   ADU = min(max(floor(R / gain + bias + 1/2), 0), 2^bits - 1)
+ * Computed for the window [x0, x0+w) x [y0, y0+h) of an nx x ny frame;
+ * r_out (optional) receives R.
+ */
+void orc_detector(const double *F, const double *G, int nx, int ny, int x0, int y0, int w,
+                  int h, double exposure_s, double dark_e_per_s, int shot_noise,
+                  const double *K, double ron_e, double gain, double bias, int bits,
+                  uint64_t seed, uint32_t frame, uint16_t *adu_out, double *r_out)
+{
+    const double dt = dark_e_per_s * exposure_s;
+    const double top = (double)((1u << bits) - 1u);
+    /* electrons of the window and its one-pixel border */
+    int bx0 = x0 - 1, by0 = y0 - 1, bw = w + 2, bh = h + 2;
+    double *N = (double *)calloc((size_t)bw * bh, sizeof(double));
+    for (int j = 0; j < bh; ++j) {
+        int gy = by0 + j;
+        if (gy < 0 || gy >= ny) continue;
+        for (int i = 0; i < bw; ++i) {
+            int gx = bx0 + i;
+            if (gx < 0 || gx >= nx) continue;
+            int64_t p = (int64_t)gy * nx + gx;
+            double g = G ? G[p] : 1.0;
+            double mu = fma(g, F[p], dt);
+            if (shot_noise) {
+                orc_stream st;
+                st.key[0] = (uint32_t)seed; st.key[1] = (uint32_t)(seed >> 32);
+                st.ctr[0] = (uint32_t)p; st.ctr[1] = (uint32_t)((uint64_t)p >> 32);
+                st.ctr[2] = frame; st.ctr[3] = 0;
+                st.have = 0;
+                N[(size_t)j * bw + i] = poisson_draw(mu, &st);
+            } else {
+                N[(size_t)j * bw + i] = mu;
+            }
+        }
+    }
+    for (int j = 0; j < h; ++j) {
+        for (int i = 0; i < w; ++i) {
+            int gx = x0 + i, gy = y0 + j;
+            int64_t p = (int64_t)gy * nx + gx;
+            double e = 0.0;
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    /* source pixel (gx - dx, gy - dy) in border coordinates */
+                    int si = (gx - dx) - bx0, sj = (gy - dy) - by0;
+                    e = fma(K[(dy + 1) * 3 + (dx + 1)], N[(size_t)sj * bw + si], e);
+                }
+            double r = e;
+            if (ron_e > 0.0) {
+                uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+                uint32_t ctr[4] = {(uint32_t)p, (uint32_t)((uint64_t)p >> 32), frame, 0x80000000u};
+                uint32_t b[4];
+                orc_philox4x32_10(ctr, key, b);
+                double u1 = u53(b[0], b[1]), u2 = u53(b[2], b[3]);
+                double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+                r = fma(ron_e, z, e);
+            }
+            if (r_out) r_out[(size_t)j * w + i] = r;
+            double v = floor(r / gain + bias + 0.5);
+            if (v < 0.0) v = 0.0;
+            if (v > top) v = top;
+            adu_out[(size_t)j * w + i] = (uint16_t)v;
+        }
+    }
+    free(N);
+}

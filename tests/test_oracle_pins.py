@@ -448,3 +448,108 @@ def test_poisson_sampler_chi2(lam):
     chi2 = ((obs[keep] - exp[keep]) ** 2 / exp[keep]).sum()
     dof = keep.sum() - 1
     assert stats.chi2.sf(chi2, dof) > 1e-4
+
+
+# ------------------------------------------------------------ detector stage
+# Sec. 2.2: photon noise and the detector's noises (dark current, read-out
+# noise, pixel response non-uniformity, cross-talk) on the final frame.
+
+_K = np.array([[0.002, 0.011, 0.003],
+               [0.017, 0.930, 0.013],
+               [0.004, 0.015, 0.005]])
+
+
+def test_detector_noise_free_is_rounding():
+    """D1: no shot or read noise, unit gain, identity cross-talk: the ADU is
+    round-half-up of the counts, clipped to the ADC range."""
+    F = np.array([[0.0, 0.49, 0.5, 1.5, 2.5, 1e9, -3.0, 65535.4, 65535.5, 17.0]])
+    a = oracle.detector(F, shot_noise=False)
+    want = np.clip(np.floor(F + 0.5), 0, 65535)
+    assert np.array_equal(a.astype(float), want)
+    a12 = oracle.detector(F, shot_noise=False, bits=12)
+    assert a12.max() == 4095
+
+
+def test_detector_crosstalk_point_source_and_edges():
+    """D2: a point source spreads as the kernel (charge moves from a pixel to
+    its neighbour at offset (dx, dy) with weight K[dy+1][dx+1]); inside the
+    chip the total is V sum(K); at a corner the part leaving the chip is
+    lost."""
+    V = 1.0e4
+    F = np.zeros((9, 11))
+    F[4, 6] = V
+    a, r = oracle.detector(F, shot_noise=False, xtalk=_K, want_r=True)
+    assert np.allclose(r[3:6, 5:8], V * _K, rtol=1e-14, atol=0)
+    assert np.count_nonzero(r) == 9
+    assert abs(r.sum() - V * _K.sum()) < 1e-9
+    F = np.zeros((9, 11))
+    F[0, 0] = V
+    _, r = oracle.detector(F, shot_noise=False, xtalk=_K, want_r=True)
+    assert abs(r.sum() - V * _K[1:, 1:].sum()) < 1e-9  # up and left fell off
+
+
+def test_detector_prnu_dark_gain_bias():
+    """D3: noise-free chain with a PRNU map, dark current, gain and bias
+    equals the affine map of the counts (identity cross-talk)."""
+    rng = np.random.default_rng(3)
+    F = rng.uniform(0, 5e4, (16, 24))
+    G = rng.uniform(0.97, 1.03, F.shape)
+    a, r = oracle.detector(F, prnu=G, exposure_s=300.0, dark_e_per_s=0.01,
+                           shot_noise=False, gain=1.7, bias=1000.0, want_r=True)
+    e = G * F + 3.0
+    assert np.allclose(r, e, rtol=1e-15, atol=1e-9)
+    want = np.clip(np.floor(e / 1.7 + 1000.0 + 0.5), 0, 65535)
+    assert np.array_equal(a.astype(float), want)
+
+
+def test_detector_read_noise_box_muller_closed_form():
+    """D4: with no signal the read noise of pixel p is ron sqrt(-2 ln u1)
+    cos(2 pi u2), u1, u2 the 53-bit uniforms of words 0-1 and 2-3 of the
+    pixel's Philox block 2^31 (the raw stream is the pinned generator)."""
+    ny, nx = 3, 5
+    ron = 4.5
+    _, r = oracle.detector(np.zeros((ny, nx)), shot_noise=False, ron_e=ron, seed=11, frame=2,
+                           want_r=True)
+    for p in range(ny * nx):
+        w = oracle.philox4x32_10([p, 0, 2, 0x80000000], [11, 0]).astype(np.uint64)
+        u1 = (((w[0] >> 5) << 26) | (w[1] >> 6)).astype(np.float64) + 0.5
+        u2 = (((w[2] >> 5) << 26) | (w[3] >> 6)).astype(np.float64) + 0.5
+        u1, u2 = u1 / 2.0 ** 53, u2 / 2.0 ** 53
+        z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+        assert abs(r.flat[p] - ron * z) < 1e-12 * ron
+
+
+def test_detector_read_noise_is_normal():
+    """D5: read noise alone is N(0, ron^2) (moments and Kolmogorov-Smirnov)."""
+    ron = 6.0
+    _, r = oracle.detector(np.zeros((300, 300)), shot_noise=False, ron_e=ron, seed=5,
+                           want_r=True)
+    z = r.ravel() / ron
+    assert abs(z.mean()) < 5 / 300
+    assert abs(z.std() - 1) < 0.01
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+
+
+def test_detector_shot_noise_is_the_poisson_stream():
+    """D6: shot noise alone (unit gain, identity cross-talk) gives the
+    Poisson draws of the pixel's own stream, i.e. the pinned sampler."""
+    rng = np.random.default_rng(4)
+    F = rng.uniform(0, 300, (20, 30))
+    F[0, :5] = [0.0, 0.2, 9.99, 10.0, 2e4]
+    a = oracle.detector(F, exposure_s=10.0, dark_e_per_s=0.05, seed=9, frame=7)
+    want = oracle.poisson_frame((F + 0.5).ravel(), 9, 7).reshape(F.shape)
+    assert np.array_equal(a.astype(float), want)
+
+
+def test_detector_full_chain_moments():
+    """D7: the whole chain on a flat field: E[ADU] = (sum(K) mu)/g + b and
+    Var[ADU] = (sum(K^2) mu + ron^2)/g^2 + 1/12 (quantisation), away from
+    the edges (shot noise of different pixels is independent)."""
+    mu, ron, g, b = 2500.0, 7.0, 1.3, 500.0
+    F = np.full((260, 260), mu)
+    a = oracle.detector(F, shot_noise=True, xtalk=_K, ron_e=ron, gain=g, bias=b, seed=21)
+    x = a[2:-2, 2:-2].astype(float).ravel()
+    m_want = _K.sum() * mu / g + b
+    v_want = ((_K ** 2).sum() * mu + ron ** 2) / g ** 2 + 1.0 / 12.0
+    assert abs(x.mean() - m_want) < 5 * np.sqrt(v_want / x.size) + 0.01
+    assert abs(x.var() / v_want - 1) < 0.03
