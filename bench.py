@@ -207,7 +207,36 @@ def secondary(E, P, torch, ctx, sc1, ld1, specs1, log):
     res["noise_c1"] = {"kernel_ms": ms, "bytes_per_launch": nbytes,
                        "achieved_GBps": nbytes / (ms / 1e3) / 1e9,
                        "hbm_frac": nbytes / (ms / 1e3) / PEAK_HBM}
-    del out1
+
+    log("secondary: detector stage on the c1 frame")
+    from workloads import XTALK_CCD, prnu_map
+    g1 = torch.from_numpy(prnu_map(sc1.nx, sc1.ny, 1001)).to("cuda")
+    adu = torch.empty((sc1.ny, sc1.nx), dtype=torch.int16, device="cuda")
+    det = {}
+    for label, shot, ron in (("shot_read_noise", 1, 3.0), ("noise_free", 0, 0.0)):
+        d = E.e2e_detector_desc()
+        for q, v in enumerate(XTALK_CCD.reshape(9)):
+            d.xtalk[q] = float(v)
+        d.exposure_s, d.dark_e_per_s, d.ron_e = 900.0, 0.011, ron
+        d.gain_e_per_adu, d.bias_adu, d.bits, d.shot_noise = 1.37, 1000.0, 16, shot
+        d.seed, d.frame_index = 5, 1
+
+        def run(d=d):
+            E.e2e_detector(ctx, d, out1.data_ptr(), E.E2E_F32, g1.data_ptr(), sc1.nx, sc1.ny,
+                           adu.data_ptr(), 1)
+        px = sc1.nx * sc1.ny
+        ms_e = kernel_ms(run, "detector_electrons")
+        ms_a = kernel_ms(run, "detector_adc")
+        # algorithmic bytes: frame + gains in, FP64 electrons out; electrons
+        # in, uint16 ADU out
+        be, ba = px * (4 + 4 + 8), px * (8 + 2)
+        det[label] = {"electrons_ms": ms_e, "adc_ms": ms_a, "stage_ms": ms_e + ms_a,
+                      "electrons_GBps": be / (ms_e / 1e3) / 1e9,
+                      "adc_GBps": ba / (ms_a / 1e3) / 1e9,
+                      "stage_px_per_s": px / ((ms_e + ms_a) / 1e3),
+                      "min_bytes_per_px": 10, "stage_bytes_per_px": 26}
+    res["detector_c1"] = det
+    del out1, g1, adu
 
     log("secondary: c4 HIRES-shaped frame")
     c4 = scene("c4")

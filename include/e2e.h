@@ -249,6 +249,54 @@ e2e_status e2e_noise_poisson(e2e_ctx *ctx, void *frame, int32_t dtype, int64_t n
                              uint64_t seed, uint32_t frame_index, int32_t on_device,
                              void *hip_stream);
 /*
+ * Detector stage on a rendered frame (Sec. 2.2: the frame of expected
+ * photo-electrons is turned into a raw CCD read-out by photon noise plus the
+ * detector's own effects -- dark current, read-out noise, pixel response
+ * non-uniformity and inter-pixel cross-talk -- then digitised).  For pixel
+ * p = y nx + x, in this order:
+ *   mu  = G[p] F[p] + dark_e_per_s exposure_s  (one FP64 fma; G = prnu, 1 if
+ *         prnu is NULL)
+ *   N   = Poisson(mu) from pixel p's counter stream (the stream of
+ *         e2e_noise_poisson: Philox blocks 0, 1, ...), or mu if shot_noise = 0
+ *   E   = sum over dy = -1..1 (outer), dx = -1..1 (inner) of
+ *         xtalk[(dy+1)*3 + dx+1] * N[(x-dx, y-dy)], FP64 fma in that order;
+ *         a source pixel off the detector contributes 0 (xtalk[4] is the
+ *         charge a pixel keeps, xtalk[(dy+1)*3+dx+1] what it hands to its
+ *         neighbour at offset (dx, dy))
+ *   R   = E + ron_e Z, Z = sqrt(-2 ln u1) cos(2 pi u2) from Philox block
+ *         2^31 of pixel p's stream (u1 from words 0-1, u2 from words 2-3,
+ *         53-bit uniforms in (0, 1)); skipped when ron_e = 0
+ *   ADU = min(max(floor(R / gain_e_per_adu + bias_adu + 1/2), 0), 2^bits - 1)
+ * frame: nx * ny row-major values of frame_dtype (E2E_F32 / E2E_F64) in
+ * expected electrons; prnu: NULL or nx * ny FP32 gains; adu_out: nx * ny
+ * uint16.  on_device = 1: all three are device pointers and the call is
+ * ordered on hip_stream (NULL: the context's stream), returning after the
+ * work is enqueued and finished; 0: host pointers, staged through device
+ * memory.  The caller owns all buffers; the library allocates an FP64
+ * electron frame of nx * ny doubles for the call.
+ * Errors: E2E_EINVAL for NULL ctx / desc / frame / adu_out, nx or ny < 0,
+ * bad dtype, bits outside 1..16, gain_e_per_adu <= 0, a negative or
+ * non-finite exposure, dark current or read noise, or non-finite cross-talk
+ * weights or bias; E2E_ENOMEM, E2E_EDEVICE.
+ */
+typedef struct {
+    double exposure_s;         /* t [s]                                         */
+    double dark_e_per_s;       /* dark current [e-/s/pixel]                     */
+    double xtalk[9];           /* K[dy+1][dx+1], row-major                      */
+    double ron_e;              /* read-out noise sigma [e-]                     */
+    double gain_e_per_adu;     /* electrons per ADU                             */
+    double bias_adu;           /* offset added before rounding                  */
+    uint64_t seed;
+    uint32_t frame_index;
+    int32_t shot_noise;        /* 1: Poisson draw of mu, 0: mu itself           */
+    int32_t bits;              /* ADC resolution, 1..16                         */
+    int32_t reserved;
+} e2e_detector_desc;
+e2e_status e2e_detector(e2e_ctx *ctx, const e2e_detector_desc *d, const void *frame,
+                        int32_t frame_dtype, const float *prnu, int32_t nx, int32_t ny,
+                        uint16_t *adu_out, int32_t on_device, void *hip_stream);
+
+/*
  * Raw Philox-4x32-10 blocks (Salmon et al., SC'11) of the noise stream:
  * out_host[(p * blocks + b) * 4 + w] = word w of block b of pixel pixel0+p.
  */

@@ -929,6 +929,76 @@ extern "C" e2e_status e2e_noise_poisson(e2e_ctx *ctx, void *frame, int32_t dtype
     return E2E_OK;
 }
 
+extern "C" e2e_status e2e_detector(e2e_ctx *ctx, const e2e_detector_desc *d, const void *frame,
+                                   int32_t dtype, const float *prnu, int32_t nx, int32_t ny,
+                                   uint16_t *adu_out, int32_t on_device, void *stream)
+{
+    if (!ctx || !d || !frame || !adu_out) return fail(E2E_EINVAL, "e2e_detector: NULL argument");
+    if (dtype != E2E_F32 && dtype != E2E_F64) return fail(E2E_EINVAL, "dtype=%d", dtype);
+    if (nx < 0 || ny < 0) return fail(E2E_EINVAL, "e2e_detector: nx=%d ny=%d", nx, ny);
+    if (d->bits < 1 || d->bits > 16) return fail(E2E_EINVAL, "e2e_detector: bits=%d", d->bits);
+    if (!(d->gain_e_per_adu > 0.0) || !std::isfinite(d->gain_e_per_adu))
+        return fail(E2E_EINVAL, "e2e_detector: gain_e_per_adu=%g", d->gain_e_per_adu);
+    if (!(d->exposure_s >= 0.0) || !std::isfinite(d->exposure_s) || !(d->dark_e_per_s >= 0.0) ||
+        !std::isfinite(d->dark_e_per_s) || !(d->ron_e >= 0.0) || !std::isfinite(d->ron_e) ||
+        !std::isfinite(d->bias_adu))
+        return fail(E2E_EINVAL, "e2e_detector: exposure, dark current, read noise or bias");
+    for (int q = 0; q < 9; ++q)
+        if (!std::isfinite(d->xtalk[q])) return fail(E2E_EINVAL, "e2e_detector: xtalk[%d]", q);
+    const int64_t n = (int64_t)nx * ny;
+    if (n == 0) return E2E_OK;
+    hipSetDevice(ctx->dev);
+    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    const size_t fbytes = (size_t)n * (dtype == E2E_F64 ? 8 : 4);
+    const size_t gbytes = prnu ? (size_t)n * 4 : 0;
+    const size_t obytes = (size_t)n * 2;
+    // one device block: electrons (FP64), then the staged inputs / output
+    // when the caller's buffers are on the host
+    size_t total = (size_t)n * 8;
+    size_t off_f = total, off_g = 0, off_o = 0;
+    if (!on_device) {
+        off_f = total;
+        total += (fbytes + 255) & ~(size_t)255;
+        off_g = total;
+        total += (gbytes + 255) & ~(size_t)255;
+        off_o = total;
+        total += (obytes + 255) & ~(size_t)255;
+    }
+    char *blk = nullptr;
+    hipError_t e = hipMalloc((void **)&blk, total);
+    if (e != hipSuccess) return hip_fail(e, "detector buffers");
+    double *el = (double *)blk;
+    const void *fd = frame;
+    const float *gd = prnu;
+    uint16_t *od = adu_out;
+    if (!on_device) {
+        fd = blk + off_f;
+        gd = prnu ? (const float *)(blk + off_g) : nullptr;
+        od = (uint16_t *)(blk + off_o);
+        e = hipMemcpyAsync((void *)fd, frame, fbytes, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && prnu)
+            e = hipMemcpyAsync((void *)gd, prnu, gbytes, hipMemcpyHostToDevice, s);
+    }
+    if (e == hipSuccess) {
+        prof_begin(ctx, s, "detector_electrons");
+        e = launch_det_electrons(fd, dtype == E2E_F64, gd, n, d->dark_e_per_s * d->exposure_s,
+                                 d->shot_noise != 0, d->seed, d->frame_index, el, s);
+        prof_end(ctx, s);
+    }
+    if (e == hipSuccess) {
+        prof_begin(ctx, s, "detector_adc");
+        e = launch_det_adc(el, nx, ny, d->xtalk, d->ron_e, d->gain_e_per_adu, d->bias_adu,
+                           d->bits, d->seed, d->frame_index, od, s);
+        prof_end(ctx, s);
+    }
+    if (e == hipSuccess && !on_device)
+        e = hipMemcpyAsync(adu_out, od, obytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(blk);
+    if (e != hipSuccess) return hip_fail(e, "e2e_detector");
+    return E2E_OK;
+}
+
 extern "C" e2e_status e2e_philox_blocks(e2e_ctx *ctx, uint64_t seed, uint32_t fidx,
                                         uint64_t pixel0, int64_t n, uint32_t blocks,
                                         uint32_t *out)

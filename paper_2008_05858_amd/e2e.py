@@ -30,7 +30,7 @@ EXPORTS = ["e2e_create", "e2e_destroy", "e2e_last_error", "e2e_version", "e2e_fo
            "e2e_psf_load", "e2e_format_free", "e2e_psf_free", "e2e_render", "e2e_render_batch",
            "e2e_serve_start", "e2e_serve_submit", "e2e_serve_poll", "e2e_serve_stop",
            "e2e_noise_poisson", "e2e_philox_blocks", "e2e_set_profiling", "e2e_kernel_time",
-           "e2e_reset_kernel_time", "e2e_autotune"]
+           "e2e_reset_kernel_time", "e2e_autotune", "e2e_detector"]
 E2E_TUNE_MAX = 16
 
 
@@ -65,6 +65,14 @@ class e2e_tune_report(C.Structure):
                 ("cand_chunk", C.c_int32 * E2E_TUNE_MAX),
                 ("cand_resident", C.c_int32 * E2E_TUNE_MAX),
                 ("cand_ms", C.c_double * E2E_TUNE_MAX)]
+
+
+class e2e_detector_desc(C.Structure):
+    _fields_ = [("exposure_s", C.c_double), ("dark_e_per_s", C.c_double),
+                ("xtalk", C.c_double * 9), ("ron_e", C.c_double),
+                ("gain_e_per_adu", C.c_double), ("bias_adu", C.c_double),
+                ("seed", C.c_uint64), ("frame_index", C.c_uint32),
+                ("shot_noise", C.c_int32), ("bits", C.c_int32), ("reserved", C.c_int32)]
 
 
 class e2e_render_stats(C.Structure):
@@ -128,6 +136,9 @@ def lib():
         L.e2e_kernel_time.argtypes = [C.c_void_p, C.c_char_p, P(C.c_int64), P(C.c_double)]
         L.e2e_reset_kernel_time.argtypes = [C.c_void_p]
         L.e2e_autotune.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, P(e2e_tune_report)]
+        L.e2e_detector.argtypes = [C.c_void_p, P(e2e_detector_desc), C.c_void_p, C.c_int32,
+                                   C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
+                                   C.c_void_p]
         for n in EXPORTS:
             if n not in ("e2e_destroy", "e2e_last_error", "e2e_version"):
                 getattr(L, n).restype = C.c_int32
@@ -215,6 +226,14 @@ def e2e_noise_poisson(ctx, frame_ptr, dtype, n_pixels, seed, frame_index, on_dev
                       stream=None):
     return check(lib().e2e_noise_poisson(ctx, frame_ptr, dtype, n_pixels, seed, frame_index,
                                          on_device, stream))
+
+
+def e2e_detector(ctx, desc, frame_ptr, frame_dtype, prnu_ptr, nx, ny, adu_ptr, on_device,
+                 stream=None):
+    """Detector stage (PRNU, dark current, shot noise, cross-talk, read noise,
+    ADC) of an nx x ny frame into uint16 ADU; pointers as in the C call."""
+    return check(lib().e2e_detector(ctx, C.byref(desc), frame_ptr, frame_dtype, prnu_ptr, nx,
+                                    ny, adu_ptr, on_device, stream))
 
 
 def e2e_philox_blocks(ctx, seed, frame_index, pixel0, n_pixels, blocks):

@@ -7,7 +7,7 @@ maps a wavelength to the detector, never integrates a PSF over a pixel and
 never accumulates a frame.
 """
 from .synth import (Trace, Psf, Scene, Request, scene, request, SCENES,
-                    CONFIG_NOTES)
+                    CONFIG_NOTES, detector_frame, prnu_map, XTALK_CCD)
 
 __all__ = ["Trace", "Psf", "Scene", "Request", "scene", "request", "SCENES",
-           "CONFIG_NOTES"]
+           "CONFIG_NOTES", "detector_frame", "prnu_map", "XTALK_CCD"]

@@ -363,3 +363,38 @@ def request(rng_or_seed=None, *, rv_range=(0.0, 0.0), flux_range=(1.0, 1.0),
 def with_traces(sc: Scene, idx) -> Scene:
     """A copy of a scene restricted to some traces (spectra shared)."""
     return dataclasses.replace(sc, traces=[sc.traces[i] for i in idx])
+
+
+def detector_frame(nx: int, ny: int, seed: int = 0, *, spacing: float = 27.0,
+                   sigma: float = 1.6, peak: float = 7e5, bg: float = 20.0,
+                   dtype=np.float32) -> np.ndarray:
+    """Expected photo-electrons [ny][nx] with an echellogram's value mix, for
+    the detector stage: curved bright bands every `spacing` rows (Gaussian
+    cross profile, blaze-shaped along x, peak about `peak`) over a faint
+    background (Sec. 4.1 frames reach a few 1e5 e- per pixel in their
+    orders)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = np.arange(nx, dtype=np.float32)[None, :]
+    y = np.arange(ny, dtype=np.float32)[:, None]
+    ph = np.float32(rng.uniform(0.0, 2 * np.pi))
+    curve = np.float32(0.5 * spacing) * np.sin(np.float32(2.6 * np.pi / max(nx, 1)) * x + ph)
+    d = np.mod(y - curve, np.float32(spacing)) - np.float32(0.5 * spacing)
+    blaze = np.float32(peak) * (np.float32(0.2) + np.float32(0.8) *
+                                np.sin(np.float32(np.pi) * (x + 0.5) / np.float32(max(nx, 1))) ** 2)
+    F = np.float32(bg) + blaze * np.exp(np.float32(-0.5) * (d / np.float32(sigma)) ** 2)
+    return np.ascontiguousarray(F.astype(dtype, copy=False))
+
+
+def prnu_map(nx: int, ny: int, seed: int = 0, rms: float = 0.01) -> np.ndarray:
+    """Pixel response map [ny][nx] (FP32): 1 + rms * N(0, 1)."""
+    rng = np.random.Generator(np.random.PCG64(seed + 0x5EED))
+    g = rng.standard_normal((ny, nx), dtype=np.float32)
+    return np.ascontiguousarray(np.float32(1.0) + np.float32(rms) * g)
+
+
+# Cross-talk kernel K[dy+1][dx+1] of a deep-depletion CCD: a pixel keeps
+# ~97.6 % of its charge and hands the rest to its four / eight neighbours,
+# slightly more along the read-out columns (values illustrative).
+XTALK_CCD = np.array([[0.0010, 0.0060, 0.0010],
+                      [0.0040, 0.9760, 0.0040],
+                      [0.0010, 0.0060, 0.0010]], dtype=np.float64)
