@@ -225,16 +225,12 @@ def secondary(E, P, torch, ctx, sc1, ld1, specs1, log):
             E.e2e_detector(ctx, d, out1.data_ptr(), E.E2E_F32, g1.data_ptr(), sc1.nx, sc1.ny,
                            adu.data_ptr(), 1)
         px = sc1.nx * sc1.ny
-        ms_e = kernel_ms(run, "detector_electrons")
-        ms_a = kernel_ms(run, "detector_adc")
-        # algorithmic bytes: frame + gains in, FP64 electrons out; electrons
-        # in, uint16 ADU out
-        be, ba = px * (4 + 4 + 8), px * (8 + 2)
-        det[label] = {"electrons_ms": ms_e, "adc_ms": ms_a, "stage_ms": ms_e + ms_a,
-                      "electrons_GBps": be / (ms_e / 1e3) / 1e9,
-                      "adc_GBps": ba / (ms_a / 1e3) / 1e9,
-                      "stage_px_per_s": px / ((ms_e + ms_a) / 1e3),
-                      "min_bytes_per_px": 10, "stage_bytes_per_px": 26}
+        ms = kernel_ms(run, "detector")
+        # algorithmic bytes: FP32 frame + FP32 gains in, uint16 ADU out
+        nb = px * (4 + 4 + 2)
+        det[label] = {"kernel_ms": ms, "bytes_per_launch": nb,
+                      "achieved_GBps": nb / (ms / 1e3) / 1e9,
+                      "hbm_frac": nb / (ms / 1e3) / PEAK_HBM, "px_per_s": px / (ms / 1e3)}
     res["detector_c1"] = det
     del out1, g1, adu
 

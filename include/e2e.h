@@ -272,9 +272,9 @@ e2e_status e2e_noise_poisson(e2e_ctx *ctx, void *frame, int32_t dtype, int64_t n
  * uint16.  on_device = 1: all three are device pointers and the call is
  * ordered on hip_stream (NULL: the context's stream), returning after the
  * work is enqueued and finished; 0: host pointers, staged through device
- * memory.  The caller owns all buffers; the library allocates an FP64
- * electron frame of nx * ny doubles for the call.
- * Errors: E2E_EINVAL for NULL ctx / desc / frame / adu_out, nx or ny < 0,
+ * memory (allocated for the call).  The caller owns all buffers.
+ * Errors: E2E_EINVAL for NULL ctx / desc / frame / adu_out, nx < 0, ny
+ * outside 0..4194240,
  * bad dtype, bits outside 1..16, gain_e_per_adu <= 0, a negative or
  * non-finite exposure, dark current or read noise, or non-finite cross-talk
  * weights or bias; E2E_ENOMEM, E2E_EDEVICE.

@@ -935,7 +935,8 @@ extern "C" e2e_status e2e_detector(e2e_ctx *ctx, const e2e_detector_desc *d, con
 {
     if (!ctx || !d || !frame || !adu_out) return fail(E2E_EINVAL, "e2e_detector: NULL argument");
     if (dtype != E2E_F32 && dtype != E2E_F64) return fail(E2E_EINVAL, "dtype=%d", dtype);
-    if (nx < 0 || ny < 0) return fail(E2E_EINVAL, "e2e_detector: nx=%d ny=%d", nx, ny);
+    if (nx < 0 || ny < 0 || ny > 65535 * 64)
+        return fail(E2E_EINVAL, "e2e_detector: nx=%d ny=%d", nx, ny);
     if (d->bits < 1 || d->bits > 16) return fail(E2E_EINVAL, "e2e_detector: bits=%d", d->bits);
     if (!(d->gain_e_per_adu > 0.0) || !std::isfinite(d->gain_e_per_adu))
         return fail(E2E_EINVAL, "e2e_detector: gain_e_per_adu=%g", d->gain_e_per_adu);
@@ -952,27 +953,18 @@ extern "C" e2e_status e2e_detector(e2e_ctx *ctx, const e2e_detector_desc *d, con
     const size_t fbytes = (size_t)n * (dtype == E2E_F64 ? 8 : 4);
     const size_t gbytes = prnu ? (size_t)n * 4 : 0;
     const size_t obytes = (size_t)n * 2;
-    // one device block: electrons (FP64), then the staged inputs / output
-    // when the caller's buffers are on the host
-    size_t total = (size_t)n * 8;
-    size_t off_f = total, off_g = 0, off_o = 0;
-    if (!on_device) {
-        off_f = total;
-        total += (fbytes + 255) & ~(size_t)255;
-        off_g = total;
-        total += (gbytes + 255) & ~(size_t)255;
-        off_o = total;
-        total += (obytes + 255) & ~(size_t)255;
-    }
-    char *blk = nullptr;
-    hipError_t e = hipMalloc((void **)&blk, total);
-    if (e != hipSuccess) return hip_fail(e, "detector buffers");
-    double *el = (double *)blk;
     const void *fd = frame;
     const float *gd = prnu;
     uint16_t *od = adu_out;
+    char *blk = nullptr;
+    hipError_t e = hipSuccess;
     if (!on_device) {
-        fd = blk + off_f;
+        // staged copies of the caller's host buffers
+        const size_t off_g = (fbytes + 255) & ~(size_t)255;
+        const size_t off_o = off_g + ((gbytes + 255) & ~(size_t)255);
+        if ((e = hipMalloc((void **)&blk, off_o + obytes)) != hipSuccess)
+            return hip_fail(e, "detector buffers");
+        fd = blk;
         gd = prnu ? (const float *)(blk + off_g) : nullptr;
         od = (uint16_t *)(blk + off_o);
         e = hipMemcpyAsync((void *)fd, frame, fbytes, hipMemcpyHostToDevice, s);
@@ -980,21 +972,16 @@ extern "C" e2e_status e2e_detector(e2e_ctx *ctx, const e2e_detector_desc *d, con
             e = hipMemcpyAsync((void *)gd, prnu, gbytes, hipMemcpyHostToDevice, s);
     }
     if (e == hipSuccess) {
-        prof_begin(ctx, s, "detector_electrons");
-        e = launch_det_electrons(fd, dtype == E2E_F64, gd, n, d->dark_e_per_s * d->exposure_s,
-                                 d->shot_noise != 0, d->seed, d->frame_index, el, s);
-        prof_end(ctx, s);
-    }
-    if (e == hipSuccess) {
-        prof_begin(ctx, s, "detector_adc");
-        e = launch_det_adc(el, nx, ny, d->xtalk, d->ron_e, d->gain_e_per_adu, d->bias_adu,
-                           d->bits, d->seed, d->frame_index, od, s);
+        prof_begin(ctx, s, "detector");
+        e = launch_detector(fd, dtype == E2E_F64, gd, nx, ny, d->dark_e_per_s * d->exposure_s,
+                            d->shot_noise != 0, d->xtalk, d->ron_e, d->gain_e_per_adu,
+                            d->bias_adu, d->bits, d->seed, d->frame_index, od, s);
         prof_end(ctx, s);
     }
     if (e == hipSuccess && !on_device)
         e = hipMemcpyAsync(adu_out, od, obytes, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipFree(blk);
+    if (blk) hipFree(blk);
     if (e != hipSuccess) return hip_fail(e, "e2e_detector");
     return E2E_OK;
 }

@@ -116,12 +116,10 @@ hipError_t launch_noise_frames(const FrameDev *frames_dev, const FrameDev *frame
 hipError_t launch_philox(uint64_t seed, uint32_t frame, uint64_t pixel0, int64_t n,
                          uint32_t blocks, uint32_t *out, hipStream_t s);
 hipError_t launch_fill_i32(int *p, int n, int v, hipStream_t s);
-hipError_t launch_det_electrons(const void *frame, int f64, const float *prnu, int64_t n,
-                               double dt, int shot, uint64_t seed, uint32_t fidx, double *el,
-                               hipStream_t s);
-hipError_t launch_det_adc(const double *el, int nx, int ny, const double *xtalk, double ron,
-                          double gain, double bias, int bits, uint64_t seed, uint32_t fidx,
-                          uint16_t *adu, hipStream_t s);
+hipError_t launch_detector(const void *frame, int f64, const float *prnu, int nx, int ny,
+                           double dark, int shot, const double *xtalk, double ron, double gain,
+                           double bias, int bits, uint64_t seed, uint32_t fidx, uint16_t *adu,
+                           hipStream_t s);
 
 // XCD-aware block order: blocks are dispatched round robin over the 8 XCDs,
 // so block b runs on XCD b % 8.  Give each XCD a contiguous run of tiles
