@@ -34,7 +34,8 @@ class _Psf(C.Structure):
     _fields_ = [("kind", C.c_int), ("sigma", C.c_double), ("half_width", C.c_int),
                 ("gx", C.c_int), ("gy", C.c_int), ("kw", C.c_int), ("kh", C.c_int),
                 ("os", C.c_int), ("tables", C.POINTER(C.c_float)),
-                ("sigma_xy", C.POINTER(C.c_float))]
+                ("sigma_xy", C.POINTER(C.c_float)), ("fiber_radius", C.c_double),
+                ("fiber_shape", C.c_int), ("subpix", C.c_int)]
 
 
 def lib():
@@ -50,6 +51,10 @@ def lib():
         L.orc_sample_weights.argtypes = [C.POINTER(_Psf), C.c_int, C.c_int, C.c_double,
                                          C.c_double, ip, ip, ip, ip, dp]
         L.orc_footprint_cap.argtypes = [C.POINTER(_Psf)]
+        L.orc_sfi_density.argtypes = [C.c_double] * 3 + [C.c_int] + [C.c_double] * 2
+        L.orc_sfi_density.restype = C.c_double
+        L.orc_gauss_legendre.argtypes = [C.c_int, dp, dp]
+        L.orc_gauss_legendre.restype = None
         L.orc_positions.argtypes = [C.POINTER(_Scene), C.c_int, C.c_double, C.c_int64,
                                     C.c_int64, dp, dp]
         L.orc_positions.restype = None
@@ -113,7 +118,7 @@ class _Marshalled:
 
 def marshal_psf(p):
     keep = []
-    kind = {"erf": 0, "table": 1, "separable": 2}[p.kind]
+    kind = {"erf": 0, "table": 1, "separable": 2, "sfi": 3}[p.kind]
     tab = sxy = None
     if p.tables is not None:
         tab = np.ascontiguousarray(p.tables, dtype=np.float32); keep.append(tab)
@@ -122,7 +127,10 @@ def marshal_psf(p):
     s = _Psf(kind, float(p.sigma), int(p.half_width), int(p.gx), int(p.gy),
              int(p.kw), int(p.kh), int(p.os),
              _ptr(tab, C.c_float) if tab is not None else None,
-             _ptr(sxy, C.c_float) if sxy is not None else None)
+             _ptr(sxy, C.c_float) if sxy is not None else None,
+             float(getattr(p, "fiber_radius", 0.0)),
+             {"disc": 0, "half_up": 1, "half_down": 2}[getattr(p, "fiber_shape", "disc")],
+             int(getattr(p, "subpix", 10)))
     return keep, s
 
 
@@ -168,6 +176,22 @@ def sample_weights(psf, nx, ny, x, y):
     if rc != 0:
         raise RuntimeError("oracle sample_weights failed")
     return i0.value, j0.value, wt[:w.value * h.value].reshape(h.value, w.value).copy()
+
+
+SFI_SHAPES = {"disc": 0, "half_up": 1, "half_down": 2}
+
+
+def sfi_density(u, v, rho, shape, sx, sy):
+    """Fiber image (disc / half-disc of radius rho) convolved with the
+    axis-aligned Gaussian (sx, sy): photon density at offset (u, v)."""
+    return lib().orc_sfi_density(float(u), float(v), float(rho), SFI_SHAPES[shape],
+                                 float(sx), float(sy))
+
+
+def gauss_legendre(n):
+    x = np.zeros(n); w = np.zeros(n)
+    lib().orc_gauss_legendre(n, _ptr(x, C.c_double), _ptr(w, C.c_double))
+    return x, w
 
 
 def positions(sc, tr, rv_mps, k0, count):

@@ -31,6 +31,14 @@
  *     pixel weight is the exact box overlap of every cell with the pixel;
  *   - a separable PSF interpolates (sigma_x, sigma_y) bilinearly and then
  *     integrates each axis like the analytic case;
+ *   - an explicit SFI (Sec. 2.2: the surface integral of the fiber's spatial
+ *     profile convolved with the PSF, on a sub-pixel grid) takes the fiber
+ *     image as a uniform disc of radius rho (or the half of it on one side
+ *     of the trace's y) centred on the sample position, the PSF as the
+ *     separable case's Gaussian, and the pixel value as the mean of the
+ *     convolution at the centres of S x S sub-pixels (S = 10 in the paper:
+ *     0.1-px sampling), over the (2H+1)^2 window, renormalised by the
+ *     window sum;
  *   - flux of pixels off the detector is dropped, never renormalised;
  *   - photon noise (Sec. 2.2: added on the final frame) is Poisson with the
  *     expected count as mean, drawn from Philox-4x32-10 (Salmon et al.,
@@ -67,6 +75,9 @@ typedef struct {
     int kw, kh, os;      /* table cells and cells per pixel */
     const float *tables; /* [gy][gx][kh][kw] */
     const float *sigma_xy; /* [gy][gx][2] */
+    double fiber_radius; /* sfi: radius of the fiber image (px)            */
+    int fiber_shape;     /* sfi: 0 disc, 1 half b >= 0, 2 half b <= 0      */
+    int subpix;          /* sfi: sub-pixels per pixel side                  */
 } orc_psf;
 
 static const double C_LIGHT = 299792458.0;
@@ -142,6 +153,92 @@ static double overlap(double lo1, double hi1, double lo2, double hi2)
     return hi > lo ? hi - lo : 0.0;
 }
 
+/* Gauss-Legendre nodes and weights on [-1, 1] (n <= 128): Newton's
+ * iteration on the three-term recurrence of the Legendre polynomials from
+ * the Chebyshev-like first guesses cos(pi (i + 3/4) / (n + 1/2)). */
+static void gauss_legendre(int n, double *x, double *w)
+{
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = cos(pi * ((double)i + 0.75) / ((double)n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / (double)k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1.0; }
+            dp = (double)n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+#define ORC_SFI_NQ 48
+
+/*
+ * Fiber image (uniform disc of radius rho, area A; or one half of it, area
+ * A/2) convolved with the axis-aligned Gaussian of (sx, sy): the photon
+ * density at offset (u, v) from the disc centre,
+ *   C(u, v) = (1/A_D) int_D N(u - a; sx) N(v - b; sy) da db.
+ * With a = rho sin(th) the chord of the disc at a is b in [-h, h],
+ * h = rho cos(th) ([0, h] or [-h, 0] for the halves); the b integral is a
+ * normal-CDF difference and the th integral, over [-pi/2, pi/2], has a
+ * smooth integrand and is taken with ORC_SFI_NQ Gauss-Legendre points
+ * (converged to rounding for rho / sigma <= 4).
+ */
+static double sfi_density(double u, double v, double rho, int shape, double sx, double sy,
+                          const double *qx, const double *qw)
+{
+    const double pi = 3.14159265358979323846;
+    double area = pi * rho * rho * (shape ? 0.5 : 1.0);
+    double acc = 0.0;
+    for (int q = 0; q < ORC_SFI_NQ; ++q) {
+        double th = 0.5 * pi * qx[q];
+        double a = rho * sin(th), h = rho * cos(th);
+        double lo = shape == 1 ? 0.0 : -h, hi = shape == 2 ? 0.0 : h;
+        double ga = exp(-0.5 * ((u - a) / sx) * ((u - a) / sx)) / (sqrt(2.0 * pi) * sx);
+        double gb = dphi((v - hi) / sy, (v - lo) / sy);
+        acc += 0.5 * pi * qw[q] * h * ga * gb;   /* da = rho cos(th) dth = h dth */
+    }
+    return acc / area;
+}
+
+/* Pixel weights of an explicit SFI centred at (x, y) over the window
+ * [a-H, a+H] x [b-H, b+H], a = floor(x+1/2), b = floor(y+1/2): the mean of
+ * sfi_density over the S x S sub-pixel centres of each pixel, renormalised
+ * by the window sum. */
+static void sfi_window(double x, double y, double rho, int shape, int S, double sx, double sy,
+                       int H, int *i0, int *j0, double *wt)
+{
+    double qx[ORC_SFI_NQ], qw[ORC_SFI_NQ];
+    gauss_legendre(ORC_SFI_NQ, qx, qw);
+    int a = (int)floor(x + 0.5), b = (int)floor(y + 0.5), n = 2 * H + 1;
+    double tot = 0.0;
+    for (int jj = 0; jj < n; ++jj)
+        for (int ii = 0; ii < n; ++ii) {
+            double acc = 0.0;
+            for (int t = 0; t < S; ++t) {
+                double v = (double)(b - H + jj) - 0.5 + ((double)t + 0.5) / S - y;
+                for (int s2 = 0; s2 < S; ++s2) {
+                    double u = (double)(a - H + ii) - 0.5 + ((double)s2 + 0.5) / S - x;
+                    acc += sfi_density(u, v, rho, shape, sx, sy, qx, qw);
+                }
+            }
+            wt[jj * n + ii] = acc / ((double)S * S);
+            tot += wt[jj * n + ii];
+        }
+    for (int q = 0; q < n * n; ++q) wt[q] /= tot;
+    *i0 = a - H;
+    *j0 = b - H;
+}
+
 /*
  * Footprint of one sample at (x, y): the weight of every pixel of a
  * (*w) x (*h) box whose lower-left pixel is (*i0, *j0).  Off-detector pixels
@@ -151,9 +248,9 @@ static double overlap(double lo1, double hi1, double lo2, double hi2)
 int orc_sample_weights(const orc_psf *p, int nx, int ny, double x, double y,
                        int *i0, int *j0, int *w, int *h, double *wt)
 {
-    if (p->kind == 0 || p->kind == 2) {
+    if (p->kind == 0 || p->kind == 2 || p->kind == 3) {
         double sx = p->sigma, sy = p->sigma;
-        if (p->kind == 2) {
+        if (p->kind == 2 || p->kind == 3) {
             int cx, cy; double fx, fy;
             node_frac(x, nx, p->gx, &cx, &fx);
             node_frac(y, ny, p->gy, &cy, &fy);
@@ -169,6 +266,14 @@ int orc_sample_weights(const orc_psf *p, int nx, int ny, double x, double y,
         int H = p->half_width, n = 2 * H + 1;
         double ex[2 * 64 + 1], ey[2 * 64 + 1];
         if (H > 64) return -1;
+        if (p->kind == 3) {
+            if (!(p->fiber_radius > 0.0) || p->subpix < 1 || p->fiber_shape < 0 ||
+                p->fiber_shape > 2)
+                return -1;
+            sfi_window(x, y, p->fiber_radius, p->fiber_shape, p->subpix, sx, sy, H, i0, j0, wt);
+            *w = n; *h = n;
+            return 0;
+        }
         *i0 = erf_axis(x, sx, H, ex);
         *j0 = erf_axis(y, sy, H, ey);
         *w = n; *h = n;
@@ -245,6 +350,20 @@ int orc_sample_weights(const orc_psf *p, int nx, int ny, double x, double y,
     free(K);
     *i0 = ia; *j0 = ja; *w = W; *h = Hh;
     return 0;
+}
+
+/* C(u, v) of sfi_density, for the pins. */
+double orc_sfi_density(double u, double v, double rho, int shape, double sx, double sy)
+{
+    double qx[ORC_SFI_NQ], qw[ORC_SFI_NQ];
+    gauss_legendre(ORC_SFI_NQ, qx, qw);
+    return sfi_density(u, v, rho, shape, sx, sy, qx, qw);
+}
+
+/* Gauss-Legendre rule of n points, for the pins. */
+void orc_gauss_legendre(int n, double *x, double *w)
+{
+    if (n >= 1 && n <= 128) gauss_legendre(n, x, w);
 }
 
 int orc_footprint_cap(const orc_psf *p)

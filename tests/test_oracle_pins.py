@@ -553,3 +553,117 @@ def test_detector_full_chain_moments():
     v_want = ((_K ** 2).sum() * mu + ron ** 2) / g ** 2 + 1.0 / 12.0
     assert abs(x.mean() - m_want) < 5 * np.sqrt(v_want / x.size) + 0.01
     assert abs(x.var() / v_want - 1) < 0.03
+
+
+# ---------------------------------------------------------------- explicit SFI
+# Fiber image (disc / half-disc) convolved with an axis-aligned Gaussian,
+# averaged over a sub-pixel grid (Sec. 2.2).
+
+def test_sfi_disc_centre_closed_form():
+    """S1: isotropic Gaussian, full disc: the density at the centre is the
+    mass of a 2-D normal inside radius rho, (1 - exp(-rho^2 / 2 s^2)), over
+    the disc area; a half disc holds half the mass on half the area."""
+    for rho, s in ((0.3, 1.0), (1.3, 0.9), (2.5, 0.8), (4.0, 1.0)):
+        want = -np.expm1(-rho * rho / (2 * s * s)) / (np.pi * rho * rho)
+        for shape in ("disc", "half_up", "half_down"):
+            got = oracle.sfi_density(0.0, 0.0, rho, shape, s, s)
+            assert abs(got - want) < 1e-14 * max(want, 1e-3), (rho, s, shape, got, want)
+
+
+def test_sfi_symmetries_and_halves():
+    """S2: the two halves add up to the disc, mirror into each other, and
+    the disc is symmetric in u and v."""
+    rng = np.random.default_rng(12)
+    for _ in range(30):
+        u, v = rng.uniform(-3, 3, 2)
+        rho, sx, sy = rng.uniform(0.3, 2.5), rng.uniform(0.6, 1.6), rng.uniform(0.6, 1.6)
+        full = oracle.sfi_density(u, v, rho, "disc", sx, sy)
+        up = oracle.sfi_density(u, v, rho, "half_up", sx, sy)
+        dn = oracle.sfi_density(u, v, rho, "half_down", sx, sy)
+        assert abs(up + dn - 2 * full) < 1e-14
+        assert abs(up - oracle.sfi_density(u, -v, rho, "half_down", sx, sy)) < 1e-15
+        assert abs(full - oracle.sfi_density(-u, v, rho, "disc", sx, sy)) < 1e-15
+        assert abs(full - oracle.sfi_density(u, -v, rho, "disc", sx, sy)) < 1e-15
+
+
+def test_sfi_density_vs_2d_quadrature():
+    """S3: brute force over the disc area with scipy's adaptive 2-D
+    quadrature, anisotropic Gaussian (catches a swapped sx / sy, a wrong
+    chord or Jacobian)."""
+    for (u, v, rho, sx, sy, shape) in ((0.4, -0.7, 1.5, 0.7, 1.3, "disc"),
+                                       (-1.1, 0.9, 2.2, 1.4, 0.6, "half_up"),
+                                       (0.2, 0.3, 0.8, 0.9, 1.1, "half_down"),
+                                       (0.9, 0.5, 2.4, 0.6, 0.7, "disc"),
+                                       (-0.3, 1.9, 2.4, 0.7, 0.6, "half_up")):
+        def f(b, a):
+            return (np.exp(-0.5 * ((u - a) / sx) ** 2 - 0.5 * ((v - b) / sy) ** 2) /
+                    (2 * np.pi * sx * sy))
+        lo = (lambda a: 0.0) if shape == "half_up" else (lambda a: -np.sqrt(rho * rho - a * a))
+        hi = (lambda a: 0.0) if shape == "half_down" else (lambda a: np.sqrt(rho * rho - a * a))
+        val, _ = integrate.dblquad(f, -rho, rho, lo, hi, epsabs=1e-13, epsrel=1e-11)
+        area = np.pi * rho * rho * (1.0 if shape == "disc" else 0.5)
+        got = oracle.sfi_density(u, v, rho, shape, sx, sy)
+        assert abs(got - val / area) < 1e-9 * (val / area), (shape, got, val / area)
+
+
+def test_sfi_total_mass_on_subpixel_grid():
+    """S4: the sub-pixel mean of the density over a window far larger than
+    the image integrates to 1 (the midpoint rule is spectrally accurate for
+    this smooth density)."""
+    S, L = 10, 9.0
+    g = (np.arange(int(2 * L * S)) + 0.5) / S - L
+    for rho, sx, sy, shape in ((1.2, 0.8, 1.1, "disc"), (2.0, 1.0, 0.9, "half_up")):
+        tot = sum(oracle.sfi_density(u, v, rho, shape, sx, sy) for u in g for v in g) / S ** 2
+        assert abs(tot - 1.0) < 1e-9, tot
+
+
+def test_sfi_limits():
+    """S5: a vanishing fiber leaves the Gaussian density.  (The opposite
+    limit, a vanishing PSF, lies outside the rho / sigma <= 4 domain of the
+    quadrature; S3 covers the edge of that domain.)"""
+    sx, sy = 0.9, 1.3
+    for (u, v) in ((0.0, 0.0), (0.7, -1.2), (-1.5, 0.4)):
+        g = np.exp(-0.5 * (u / sx) ** 2 - 0.5 * (v / sy) ** 2) / (2 * np.pi * sx * sy)
+        c = oracle.sfi_density(u, v, 0.01, "disc", sx, sy)
+        assert abs(c / g - 1) < 1e-3
+
+
+def test_sfi_window_tends_to_exact_pixel_integrals():
+    """S7: with a vanishing fiber and a fine sub-pixel grid the window is
+    the Gaussian's exact pixel integrals (the separable kind), to the
+    midpoint rule's O(1/S^2) error; anchors and axes must line up."""
+    sxy = np.array([[[0.9, 1.3]]], np.float32)
+    sep = Psf(kind="separable", half_width=4, sigma_xy=sxy)
+    sfi = Psf(kind="sfi", half_width=4, sigma_xy=sxy, fiber_radius=0.01, subpix=24)
+    for (x, y) in ((30.37, 20.81), (31.5, 19.02), (29.96, 20.49)):
+        i0, j0, ws = oracle.sample_weights(sep, 64, 64, x, y)
+        k0, l0, wf = oracle.sample_weights(sfi, 64, 64, x, y)
+        assert (i0, j0) == (k0, l0)
+        assert np.abs(wf - ws).max() < 5e-4 * ws.max()
+        assert abs(wf.sum() - 1) < 1e-12
+
+
+def test_sfi_frame_flux_and_centroid():
+    """S8: a rendered SFI frame conserves the photons on chip; a full-disc
+    SFI at a pixel centre (window symmetric about the sample) has its
+    photocentre at the sample position; a half disc b >= 0 moves it by the
+    half-disc centroid 4 rho / (3 pi) towards +y (a convolution adds
+    centroids), up to the window's tail truncation."""
+    sxy = np.full((2, 2, 2), 1.0, np.float32)
+    psf = Psf(kind="sfi", half_width=5, sigma_xy=sxy, fiber_radius=1.2, subpix=10)
+    sc = one_trace_scene([60.0, 40.0], [30.0, 2.0], n=60, nx=128, ny=64, psf=psf)
+    F = oracle.render(sc)
+    assert abs(F.sum() - 60.0) < 1e-10
+    for (x, y) in ((50.0, 30.0), (70.0, 31.0)):
+        i0, j0, w = oracle.sample_weights(psf, 128, 64, x, y)
+        cx = (w.sum(0) * (i0 + np.arange(w.shape[1]))).sum()
+        cy = (w.sum(1) * (j0 + np.arange(w.shape[0]))).sum()
+        assert abs(cx - x) < 1e-12 and abs(cy - y) < 1e-12
+    hp = Psf(kind="sfi", half_width=7, sigma_xy=sxy, fiber_radius=1.2, fiber_shape="half_up",
+             subpix=10)
+    for (x, y) in ((50.0, 30.0), (70.3, 31.6)):
+        i0, j0, w = oracle.sample_weights(hp, 128, 64, x, y)
+        cx = (w.sum(0) * (i0 + np.arange(w.shape[1]))).sum()
+        cy = (w.sum(1) * (j0 + np.arange(w.shape[0]))).sum()
+        assert abs(cy - y - 4 * 1.2 / (3 * np.pi)) < 1e-6, cy - y
+        assert abs(cx - x) < 1e-6

@@ -49,9 +49,9 @@ class Trace:
 
 @dataclass
 class Psf:
-    kind: str                          # 'erf' | 'table' | 'separable'
+    kind: str                          # 'erf' | 'table' | 'separable' | 'sfi'
     sigma: float = 0.0                 # erf: Gaussian sigma in px
-    half_width: int = 0                # erf / separable: footprint radius H
+    half_width: int = 0                # erf / separable / sfi: footprint radius H
     gx: int = 1
     gy: int = 1
     kw: int = 0
@@ -59,6 +59,9 @@ class Psf:
     os: int = 4
     tables: Optional[np.ndarray] = None    # [gy][gx][kh][kw] float32
     sigma_xy: Optional[np.ndarray] = None  # [gy][gx][2] float32 (sx, sy)
+    fiber_radius: float = 0.0          # sfi: fiber image radius in px
+    fiber_shape: str = "disc"          # sfi: 'disc' | 'half_up' | 'half_down'
+    subpix: int = 10                   # sfi: sub-pixels per pixel side
 
 
 @dataclass
