@@ -245,6 +245,24 @@ def secondary(E, P, torch, ctx, sc1, ld1, specs1, log):
     res["c4_table"] = {"kernel_ms": ms, "updates_per_s": c4.updates() / (ms / 1e3),
                        "frames_per_s": 1e3 / ms, "samples": c4.n_samples}
     ld4.free()
+    del sp4, out4
+
+    log("secondary: c5 explicit-SFI frame")
+    c5 = scene("c5_sfi")
+    ld5 = P.Loaded(ctx, c5)
+    sp5 = [torch.from_numpy(s).to("cuda") for s in c5.spectra]
+    out5 = torch.empty((c5.ny, c5.nx), dtype=torch.float32, device="cuda")
+    r, k = P.make_req(ld5, [s.data_ptr() for s in sp5], E.E2E_F32, out5.data_ptr(),
+                      E.E2E_F32, spectra_on_device=True, out_on_device=True, rv_mps=500.0)
+    ms = kernel_ms(lambda: E.e2e_render(ctx, r), "render_sfi")
+    n_sfi = c5.n_samples
+    w = 2 * c5.psf.half_width + 1
+    res["c5_sfi"] = {"kernel_ms": ms, "sfi": n_sfi, "sfi_per_s": n_sfi / (ms / 1e3),
+                     "subpixel_evals_per_s": n_sfi * w * w * c5.psf.subpix ** 2 / (ms / 1e3),
+                     "window_px": w, "subpixels": c5.psf.subpix,
+                     "fiber_radius_px": c5.psf.fiber_radius,
+                     "paper_s_per_sfi_k80": 0.17}
+    ld5.free()
     return res
 
 

@@ -65,6 +65,12 @@ typedef uint64_t e2e_ticket;
 #define E2E_PSF_GAUSS_ERF 0  /* circular Gaussian, exact pixel integrals       */
 #define E2E_PSF_TABLE 1      /* field-varying maps of cell integrals           */
 #define E2E_PSF_SEPARABLE 2  /* field-varying axis-aligned Gaussian (sx, sy)   */
+#define E2E_PSF_SFI 3        /* fiber image (disc / half) (x) Gaussian, sub-px */
+
+/* fiber image shapes of E2E_PSF_SFI */
+#define E2E_FIBER_DISC 0      /* uniform disc of radius fiber_radius           */
+#define E2E_FIBER_HALF_UP 1   /* its half at y >= the sample's y               */
+#define E2E_FIBER_HALF_DOWN 2 /* its half at y <= the sample's y               */
 
 /* arithmetic of the render path */
 #define E2E_PREC_F64 0       /* FP64 positions, FP32 PSF offsets, FP64 sums    */
@@ -101,6 +107,16 @@ typedef struct {
  * bilinearly at each sample's (x, y); the GPU path needs oversample = 4 and
  * kw = kh in {32, 48}.  SEPARABLE: sigma_xy[grid_ny][grid_nx][2] (sx, sy)
  * interpolated bilinearly, then the GAUSS_ERF rule per axis with half_width.
+ * SFI (Sec. 2.2: each spectral fiber image is the surface integral of the
+ * fiber's spatial profile convolved with the PSF, computed on a sub-pixel
+ * grid): the fiber image is a uniform disc of radius fiber_radius px (or
+ * the half of it selected by fiber_shape) centred on the sample position,
+ * convolved with the SEPARABLE kind's Gaussian (sigma_xy grid); a pixel's
+ * weight is the mean of that density at the centres of its subpixels x
+ * subpixels sub-pixels (10 in the paper), over the (2H+1)^2 window around
+ * (floor(x+1/2), floor(y+1/2)), renormalised by the window sum.  Limits:
+ * half_width 1..7, subpixels 1..16, fiber_radius > 0 with fiber_radius /
+ * min(sigma) <= 4 (E2E_EPSF otherwise).
  * All arrays are host memory, copied by the load call.
  */
 typedef struct {
@@ -111,6 +127,9 @@ typedef struct {
     int32_t kw, kh, oversample;
     const float *tables;
     const float *sigma_xy;
+    double fiber_radius;          /* SFI only                                  */
+    int32_t fiber_shape;          /* SFI only: E2E_FIBER_*                     */
+    int32_t subpixels;            /* SFI only                                  */
 } e2e_psf_desc;
 
 /*
@@ -308,7 +327,8 @@ e2e_status e2e_philox_blocks(e2e_ctx *ctx, uint64_t seed, uint32_t frame_index,
  * Kernel timing: with profiling on, the library brackets each launch of its
  * render kernels with HIP events on the launch stream.  e2e_kernel_time
  * returns launches and total milliseconds per kernel name ("render_table",
- * "render_sep", "render_sep_mfma", "plan", "noise"), synchronising first.
+ * "render_sep", "render_sep_mfma", "render_sfi", "plan", "noise",
+ * "detector"), synchronising first.
  */
 e2e_status e2e_set_profiling(e2e_ctx *ctx, int32_t on);
 e2e_status e2e_kernel_time(e2e_ctx *ctx, const char *kernel, int64_t *launches,

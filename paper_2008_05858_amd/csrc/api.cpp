@@ -266,6 +266,32 @@ static void node_taps(const float *K, int kw, double *tb)
                 tb[((size_t)s * OS + p) * DD + dd] = box(OS * dd - p, kw - 1 - s);
 }
 
+// Gauss-Legendre rule of n points on [-1, 1]: Newton's method on P_n from
+// the asymptotic guesses cos(pi (4i - 1) / (4n + 2)), P_n and P_n' by the
+// three-term recurrence; weights 2 / ((1 - x^2) P_n'(x)^2).
+static void legendre_rule(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 1; i <= n; ++i) {
+        double z = std::cos(M_PI * (4.0 * i - 1.0) / (4.0 * n + 2.0)), d = 1.0;
+        for (int it = 0; it < 64; ++it) {
+            double pm = 1.0, pc = z;
+            for (int k = 2; k <= n; ++k) {
+                const double pn = ((2 * k - 1) * z * pc - (k - 1) * pm) / k;
+                pm = pc;
+                pc = pn;
+            }
+            d = n * (pm - z * pc) / (1.0 - z * z);
+            const double step = pc / d;
+            z -= step;
+            if (std::fabs(step) <= 1e-16) break;
+        }
+        x[i - 1] = z;
+        w[i - 1] = 2.0 / ((1.0 - z * z) * d * d);
+    }
+}
+
 extern "C" e2e_status e2e_psf_load(e2e_ctx *ctx, const e2e_psf_desc *d, e2e_psf_id *out)
 {
     if (!ctx || !d || !out) return fail(E2E_EINVAL, "e2e_psf_load: NULL argument");
@@ -279,7 +305,7 @@ extern "C" e2e_status e2e_psf_load(e2e_ctx *ctx, const e2e_psf_desc *d, e2e_psf_
     P->kh = d->kh;
     P->os = d->oversample;
     std::vector<double> tb;
-    std::vector<float> sxy;
+    std::vector<float> sxy, sfq;
     auto bad = [&](e2e_status c, const char *m) {
         delete P;
         return fail(c, "e2e_psf_load: %s", m);
@@ -297,6 +323,45 @@ extern "C" e2e_status e2e_psf_load(e2e_ctx *ctx, const e2e_psf_desc *d, e2e_psf_
         sxy.assign(d->sigma_xy, d->sigma_xy + nn);
         for (float v : sxy)
             if (!(std::isfinite(v) && v > 0)) return bad(E2E_EPSF, "sigma_xy must be > 0");
+    } else if (d->kind == E2E_PSF_SFI) {
+        if (d->half_width < 1 || d->half_width > kSfiMaxH)
+            return bad(E2E_EPSF, "half_width outside 1..7");
+        if (d->subpixels < 1 || d->subpixels > 16) return bad(E2E_EPSF, "subpixels outside 1..16");
+        if (d->fiber_shape < E2E_FIBER_DISC || d->fiber_shape > E2E_FIBER_HALF_DOWN)
+            return bad(E2E_EPSF, "unknown fiber shape");
+        if (d->grid_nx < 1 || d->grid_ny < 1 || d->grid_nx > 127 || d->grid_ny > 127)
+            return bad(E2E_EPSF, "grid outside 1..127");
+        if (!d->sigma_xy) return bad(E2E_EINVAL, "sigma_xy is NULL");
+        size_t nn = (size_t)d->grid_nx * d->grid_ny * 2;
+        sxy.assign(d->sigma_xy, d->sigma_xy + nn);
+        float smin = 1e30f;
+        for (float v : sxy) {
+            if (!(std::isfinite(v) && v > 0)) return bad(E2E_EPSF, "sigma_xy must be > 0");
+            smin = std::min(smin, v);
+        }
+        const double rho = d->fiber_radius;
+        if (!(std::isfinite(rho) && rho > 0)) return bad(E2E_EPSF, "fiber_radius must be > 0");
+        const double r = rho / smin;
+        if (r > 4.0) return bad(E2E_EPSF, "fiber_radius / min(sigma) exceeds 4");
+        // Gauss-Legendre points over the fiber's chord angle: enough for
+        // rounding-level agreement with the converged integral up to
+        // rho / sigma = 4; an even count pairs th with -th, which share
+        // the chord half-length, so only the positive half is kept
+        int Q = 2 * (int)std::ceil((8.0 + 5.0 * r) / 2.0);
+        Q = std::min(2 * kSfiMaxR, std::max(12, Q));
+        std::vector<double> gx, gw;
+        legendre_rule(Q, gx, gw);
+        for (int q = 0; q < Q; ++q) {
+            if (gx[q] <= 0.0) continue;
+            const double th = 0.5 * M_PI * gx[q];
+            sfq.push_back((float)(rho * std::sin(th)));
+            sfq.push_back((float)(rho * std::cos(th)));
+            sfq.push_back((float)(gw[q] * std::cos(th)));
+        }
+        P->sfi_R = (int)sfq.size() / 3;
+        P->sfi_S = d->subpixels;
+        P->sfi_shape = d->fiber_shape;
+        P->rho = rho;
     } else if (d->kind == E2E_PSF_TABLE) {
         if (d->grid_nx < 1 || d->grid_ny < 1 || d->grid_nx > 127 || d->grid_ny > 127)
             return bad(E2E_EPSF, "grid outside 1..127");
@@ -326,7 +391,7 @@ extern "C" e2e_status e2e_psf_load(e2e_ctx *ctx, const e2e_psf_desc *d, e2e_psf_
     }
     hipSetDevice(ctx->dev);
     std::vector<float> tbf(tb.begin(), tb.end());
-    size_t bytes = tbf.size() * sizeof(float) + sxy.size() * sizeof(float);
+    size_t bytes = (tbf.size() + sxy.size() + sfq.size()) * sizeof(float);
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (ctx->used + bytes > ctx->budget) return bad(E2E_ENOMEM, "tables exceed the HBM budget");
     hipError_t e = hipSuccess;
@@ -340,9 +405,15 @@ extern "C" e2e_status e2e_psf_load(e2e_ctx *ctx, const e2e_psf_desc *d, e2e_psf_
         if (e == hipSuccess)
             e = hipMemcpy(P->sxy, sxy.data(), sxy.size() * sizeof(float), hipMemcpyHostToDevice);
     }
+    if (e == hipSuccess && !sfq.empty()) {
+        e = hipMalloc(&P->sfq, sfq.size() * sizeof(float));
+        if (e == hipSuccess)
+            e = hipMemcpy(P->sfq, sfq.data(), sfq.size() * sizeof(float), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         hipFree(P->tb);
         hipFree(P->sxy);
+        hipFree(P->sfq);
         delete P;
         return hip_fail(e, "e2e_psf_load");
     }
@@ -383,6 +454,7 @@ extern "C" e2e_status e2e_psf_free(e2e_ctx *ctx, e2e_psf_id id)
     hipDeviceSynchronize();
     hipFree(it->second->tb);
     hipFree(it->second->sxy);
+    hipFree(it->second->sfq);
     ctx->used -= it->second->bytes;
     delete it->second;
     ctx->psfs.erase(it);
@@ -464,6 +536,9 @@ static void tile_geom(const PsfRes *P, int precision, int *tw, int *th)
                (precision == E2E_PREC_BF16_HILO || precision == E2E_PREC_F16_HILO)) {
         *tw = kMfmaTW;
         *th = kMfmaTH;
+    } else if (P->kind == E2E_PSF_SFI) {
+        *tw = kSfiTW;
+        *th = kSfiTH;
     } else {
         *tw = *th = kSepTile;
     }
@@ -608,6 +683,10 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
         F.out = dev_out[i];
         F.tb = P->tb;
         F.sxy = P->sxy;
+        F.sfq = P->sfq;
+        F.sfi_R = P->sfi_R;
+        F.sfi_S = P->sfi_S;
+        F.sfi_shape = P->sfi_shape;
         F.segs = sc->segs + seg_off[i];
         F.tf = reinterpret_cast<TraceFrameDev *>(sc->segs + seg_total) + tf_off[i];
         F.beta = r.rv_mps / 299792458.0;
@@ -699,6 +778,9 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
                    (prec == E2E_PREC_BF16_HILO || prec == E2E_PREC_F16_HILO)) {
             prof_begin(ctx, s, "render_sep_mfma");
             q = launch_sep_mfma(sc->frames_dev, cfg, work, nwork, sc->counter, sc->err, s);
+        } else if (kind == E2E_PSF_SFI) {
+            prof_begin(ctx, s, "render_sfi");
+            q = launch_sfi(sc->frames_dev, cfg, work, nwork, sc->counter, sc->err, s);
         } else {
             prof_begin(ctx, s, "render_sep");
             q = launch_sep(sc->frames_dev, cfg, work, nwork, sc->counter, sc->err, s);

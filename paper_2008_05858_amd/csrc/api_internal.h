@@ -31,6 +31,9 @@ struct PsfRes {
     int H = 0, gx = 1, gy = 1, kw = 0, kh = 0, os = 0;
     float *tb = nullptr;    // table taps (FP32)
     float *sxy = nullptr;   // separable sigma grid
+    float *sfq = nullptr;   // SFI: quadrature nodes [R][3]
+    int sfi_R = 0, sfi_S = 0, sfi_shape = 0;
+    double rho = 0;
     size_t bytes = 0;
     int refs = 0;
 };

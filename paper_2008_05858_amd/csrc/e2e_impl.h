@@ -19,6 +19,10 @@ constexpr int kSepTile = 16;     // VALU separable / erf tile edge
 constexpr int kMfmaTW = 64;      // MFMA separable tile width (x)
 constexpr int kMfmaTH = 32;      // MFMA separable tile height (y)
 constexpr int kMaxTileTraces = 512;
+constexpr int kSfiMaxR = 16;     // SFI: quadrature node pairs (32 nodes)
+constexpr int kSfiMaxH = 7;      // SFI: footprint half width
+constexpr int kSfiTW = 64;       // SFI tile width (x)
+constexpr int kSfiTH = 32;       // SFI tile height (y)
 
 // Device-resident record of one trace (spectral-format database row).
 struct TraceDev {
@@ -57,7 +61,8 @@ struct FrameDev {
     const void *const *spec;  // device array of device pointers, per slot
     void *out;
     const float *tb;          // table path: FP32 taps [node][s][p][dd]
-    const float *sxy;         // separable: [gy][gx][2]
+    const float *sxy;         // separable / SFI: [gy][gx][2]
+    const float *sfq;         // SFI: quadrature nodes [R][3] (a_p, h_p, w_p)
     SegDev *segs;             // [ntx][ntr]
     TraceFrameDev *tf;        // [ntr]
     double beta, flux_scale;
@@ -72,6 +77,7 @@ struct FrameDev {
     int32_t poisson;
     uint32_t frame_index;
     uint64_t seed;
+    int32_t sfi_R, sfi_S, sfi_shape;  // SFI: node pairs, sub-pixels, fiber shape
 };
 
 // Device error word bits.
@@ -106,6 +112,8 @@ hipError_t launch_plan(const FrameDev *frames_dev, const FrameDev *frames_host, 
 hipError_t launch_table(const FrameDev *frames_dev, const KernelCfg &cfg, const int2 *work,
                         int n_work, int *counter, int *err, hipStream_t s);
 hipError_t launch_sep(const FrameDev *frames_dev, const KernelCfg &cfg, const int2 *work,
+                      int n_work, int *counter, int *err, hipStream_t s);
+hipError_t launch_sfi(const FrameDev *frames_dev, const KernelCfg &cfg, const int2 *work,
                       int n_work, int *counter, int *err, hipStream_t s);
 hipError_t launch_sep_mfma(const FrameDev *frames_dev, const KernelCfg &cfg, const int2 *work,
                            int n_work, int *counter, int *err, hipStream_t s);

@@ -17,7 +17,8 @@ E2E_OK, E2E_PENDING = 0, 1
 E2E_EINVAL, E2E_EFORMAT, E2E_EPSF, E2E_ENOMEM, E2E_EAGAIN = -1, -2, -3, -4, -5
 E2E_ENOTFOUND, E2E_EDEVICE, E2E_EBUSY, E2E_EUNSUPPORTED, E2E_EINTERNAL = -6, -7, -8, -9, -10
 E2E_F32, E2E_F64 = 0, 1
-E2E_PSF_GAUSS_ERF, E2E_PSF_TABLE, E2E_PSF_SEPARABLE = 0, 1, 2
+E2E_PSF_GAUSS_ERF, E2E_PSF_TABLE, E2E_PSF_SEPARABLE, E2E_PSF_SFI = 0, 1, 2, 3
+E2E_FIBER_DISC, E2E_FIBER_HALF_UP, E2E_FIBER_HALF_DOWN = 0, 1, 2
 E2E_PREC_F64, E2E_PREC_F32, E2E_PREC_BF16_HILO, E2E_PREC_F16_HILO = 0, 1, 2, 3
 E2E_FLAG_ASYNC = 1
 
@@ -46,7 +47,9 @@ class e2e_psf_desc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("sigma", C.c_double), ("half_width", C.c_int32),
                 ("grid_nx", C.c_int32), ("grid_ny", C.c_int32), ("kw", C.c_int32),
                 ("kh", C.c_int32), ("oversample", C.c_int32),
-                ("tables", C.POINTER(C.c_float)), ("sigma_xy", C.POINTER(C.c_float))]
+                ("tables", C.POINTER(C.c_float)), ("sigma_xy", C.POINTER(C.c_float)),
+                ("fiber_radius", C.c_double), ("fiber_shape", C.c_int32),
+                ("subpixels", C.c_int32)]
 
 
 class e2e_render_req(C.Structure):

@@ -14,7 +14,9 @@ import numpy as np
 from . import e2e as E
 
 _KIND = {"erf": E.E2E_PSF_GAUSS_ERF, "table": E.E2E_PSF_TABLE,
-         "separable": E.E2E_PSF_SEPARABLE}
+         "separable": E.E2E_PSF_SEPARABLE, "sfi": E.E2E_PSF_SFI}
+_FIBER = {"disc": E.E2E_FIBER_DISC, "half_up": E.E2E_FIBER_HALF_UP,
+          "half_down": E.E2E_FIBER_HALF_DOWN}
 PRECISION = {"f64": E.E2E_PREC_F64, "f32": E.E2E_PREC_F32,
              "bf16_hilo": E.E2E_PREC_BF16_HILO, "f16_hilo": E.E2E_PREC_F16_HILO}
 
@@ -47,7 +49,9 @@ def psf_desc(p):
     d = E.e2e_psf_desc(_KIND[p.kind], float(p.sigma), int(p.half_width), int(p.gx), int(p.gy),
                        int(p.kw), int(p.kh), int(p.os),
                        tab.ctypes.data_as(C.POINTER(C.c_float)) if tab is not None else None,
-                       sxy.ctypes.data_as(C.POINTER(C.c_float)) if sxy is not None else None)
+                       sxy.ctypes.data_as(C.POINTER(C.c_float)) if sxy is not None else None,
+                       float(getattr(p, "fiber_radius", 0.0)),
+                       _FIBER[getattr(p, "fiber_shape", "disc")], int(getattr(p, "subpix", 10)))
     return d, keep
 
 

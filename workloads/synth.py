@@ -81,7 +81,7 @@ class Scene:
     def footprint_px(self) -> int:
         """Pixels in one sample's PSF footprint (the update count per sample)."""
         p = self.psf
-        if p.kind in ("erf", "separable"):
+        if p.kind in ("erf", "separable", "sfi"):
             return (2 * p.half_width + 1) ** 2
         wx = (p.kw + p.os - 1) // p.os + 1
         wy = (p.kh + p.os - 1) // p.os + 1
@@ -234,6 +234,9 @@ CONFIG_NOTES: Dict[str, str] = {
     "c3v": "4096x4096, 40 orders x 1 fiber x 2 slices, 1e6 samples, c1 PSF kind",
     "c4": "6144x6144, 120 orders x 4 fibers x 3 slices, 2e6 samples, 15x15 "
           "nodes of 48x48 x4 tables",
+    "c5_sfi": "4096x4096, 40 orders x 2 fibers, 12288 samples per trace (~3 per px, "
+              "10 per resolution element), explicit SFI: disc rho=1.5 px (x) Gaussian "
+              "(sx, sy) in [0.8, 1.2] on 11x11 nodes, 11x11 px at 0.1-px sub-sampling",
 }
 
 
@@ -263,7 +266,7 @@ def _espresso(seed, *, nx, ny, orders, n_samp, gx, kwid, psf_kind, name,
               n_fib=2, n_sli=2, xc=None, xh=None, y0=300.0, pitch=100.0,
               n_lines=20000, spec_dtype=np.float32, out_dtype="f32",
               fiber_kind=("star", "fp"), a_scale=1.0, b_total=20.0,
-              sep_R=8, G=61600.0):
+              sep_R=8, G=61600.0, sfi=None, sig_range=(1.0, 1.6)):
     rng = np.random.Generator(np.random.PCG64(seed))
     xc = nx / 2.0 if xc is None else xc
     xh = 4300.0 * nx / 9216.0 if xh is None else xh
@@ -281,8 +284,15 @@ def _espresso(seed, *, nx, ny, orders, n_samp, gx, kwid, psf_kind, name,
         tabs = elliptical_gaussian_tables(rng, gx, gx, kwid, kwid, 4)
         psf = Psf(kind="table", gx=gx, gy=gx, kw=kwid, kh=kwid, os=4,
                   tables=tabs)
+    elif psf_kind == "sfi":
+        # explicit SFI (Sec. 2.2): fiber disc (or half) of radius rho px,
+        # Gaussian PSF field on the node grid, sub-pixel sampling
+        sig = rng.uniform(*sig_range, (gx, gx, 2)).astype(np.float32)
+        psf = Psf(kind="sfi", gx=gx, gy=gx, half_width=sfi.get("H", 5), sigma_xy=sig,
+                  fiber_radius=sfi.get("rho", 1.5), fiber_shape=sfi.get("shape", "disc"),
+                  subpix=sfi.get("S", 10))
     else:
-        sig = rng.uniform(1.0, 1.6, (gx, gx, 2)).astype(np.float32)
+        sig = rng.uniform(*sig_range, (gx, gx, 2)).astype(np.float32)
         psf = Psf(kind="separable", gx=gx, gy=gx, half_width=sep_R,
                   sigma_xy=sig)
     return Scene(name, nx, ny, traces, psf, spectra, out_dtype)
@@ -334,6 +344,11 @@ SCENES = {
         gx=11, kwid=32, psf_kind="table", name="c3v", n_fib=1, n_sli=2,
         fiber_kind=("star",), xh=1900.0, y0=100.0, pitch=100.0, **kw),
     "c4": lambda seed=1004, **kw: _hires(seed, **kw),
+    "c5_sfi": lambda seed=1005, **kw: _espresso(
+        seed, nx=4096, ny=4096, orders=list(range(78, 118)), n_samp=12288, gx=11, kwid=0,
+        psf_kind="sfi", name="c5_sfi", n_sli=1, xh=1900.0, y0=100.0, pitch=100.0,
+        sig_range=(0.8, 1.2), sfi=kw.pop("sfi", {"rho": 1.5, "shape": "disc", "S": 10, "H": 5}),
+        **kw),
     # reduced shapes the oracle renders in seconds; several tiles + ragged tails
     "mini_table": lambda seed=2001, **kw: _mini_table(seed, **kw),
     "mini_sep": lambda seed=2002, **kw: _espresso(
@@ -343,6 +358,12 @@ SCENES = {
     "mini_hires": lambda seed=2004, **kw: _hires(
         seed, nx=600, ny=420, n_orders=7, n_samp=12000, gx=15, kwid=48,
         name="mini_hires", n_lines=400, y0=40.0, **kw),
+    "mini_sfi": lambda seed=2005, **kw: _espresso(
+        seed, nx=120, ny=72, orders=[80], n_samp=kw.pop("n_samp", 200), gx=2, kwid=0,
+        psf_kind="sfi", name="mini_sfi", n_fib=1, n_sli=1, fiber_kind=("star",),
+        xh=40.0, y0=51.0, n_lines=20, a_scale=0.01, b_total=3.0, spec_dtype=np.float64,
+        out_dtype="f64", sig_range=(0.7, 1.2),
+        sfi=kw.pop("sfi", {"rho": 1.1, "shape": "disc", "S": 10, "H": 5}), **kw),
     "mini_c3v": lambda seed=2003, **kw: _mini_table(
         seed, nx=384, ny=320, n_orders=3, n_samp=15000, n_fib=1,
         fiber_kind=("star",), name="mini_c3v", xh=170.0, **kw),
