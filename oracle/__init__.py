@@ -70,6 +70,13 @@ def lib():
                                    C.c_double, C.c_double, C.c_int, dp, C.c_double, C.c_double,
                                    C.c_double, C.c_int, C.c_uint64, C.c_uint32, u16p, dp]
         L.orc_detector.restype = None
+        L.orc_extract.argtypes = [C.POINTER(_Scene), dp, C.c_double, dp, dp]
+        L.orc_extract.restype = None
+        L.orc_ccf.argtypes = [C.POINTER(_Scene), dp, dp, dp, C.c_double, C.c_double, C.c_int,
+                              C.c_double, dp]
+        L.orc_smooth3.argtypes = [dp, C.c_int64, C.c_int, dp]
+        L.orc_smooth3.restype = None
+        L.orc_ccf.restype = C.c_double
         _lib = L
     return _lib
 
@@ -243,3 +250,37 @@ def detector(F, *, prnu=None, exposure_s=1.0, dark_e_per_s=0.0, shot_noise=True,
                        float(bias), int(bits), int(seed), int(frame), _ptr(adu, C.c_uint16),
                        _ptr(r, C.c_double) if want_r else None)
     return (adu, r) if want_r else adu
+
+
+def extract(sc, frame, aperture_half_px):
+    """Box extraction of every trace of a rendered frame [ny][nx] (FP64
+    oracle): (E[ntr][nx], L[ntr][nx+1]) -- extracted flux per column and the
+    detector-frame wavelength of each column edge (NaN off the trace)."""
+    m = _Marshalled(sc)
+    F = np.ascontiguousarray(frame, np.float64)
+    ntr = len(sc.traces)
+    E = np.zeros((ntr, sc.nx)); L = np.zeros((ntr, sc.nx + 1))
+    lib().orc_extract(C.byref(m.scene), _ptr(F, C.c_double), float(aperture_half_px),
+                      _ptr(E, C.c_double), _ptr(L, C.c_double))
+    return E, L
+
+
+def ccf(sc, E, L, v0, dv, nv, flat=None, smooth_px=1.5):
+    """CCF of extracted spectra (divided by the extracted flat, if given)
+    against the smoothed input spectra: (C[ntr][nv], rv)."""
+    m = _Marshalled(sc)
+    E = np.ascontiguousarray(E, np.float64); L = np.ascontiguousarray(L, np.float64)
+    Ef = None if flat is None else np.ascontiguousarray(flat, np.float64)
+    Cc = np.zeros((len(sc.traces), nv))
+    rv = lib().orc_ccf(C.byref(m.scene), _ptr(E, C.c_double),
+                       _ptr(Ef, C.c_double) if Ef is not None else None, _ptr(L, C.c_double),
+                       float(v0), float(dv), int(nv), float(smooth_px), _ptr(Cc, C.c_double))
+    return Cc, rv
+
+
+def smooth3(x, w):
+    """Three passes of the clipped moving mean of odd width w."""
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.zeros_like(x)
+    lib().orc_smooth3(_ptr(x, C.c_double), x.size, int(w), _ptr(y, C.c_double))
+    return y

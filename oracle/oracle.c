@@ -657,3 +657,184 @@ void orc_detector(const double *F, const double *G, int nx, int ny, int x0, int 
     }
     free(N);
 }
+
+/* ------------------------------------------- 1-D extraction and the CCF */
+
+/*
+ * Closing the loop from the 2-D frame back to a 1-D spectrum and a radial
+ * velocity (Sec. 1: the simulator's frames feed a data-reduction pipeline;
+ * Sec. 4.2: spectra extracted along the traced orders, wavelength scale
+ * from the dispersion, RV recovered by cross-correlation).
+ *
+ * Detector-frame wavelength of a format coordinate t: lambda(t) =
+ * (t (lmax - lmin) + lmin + lmax) / 2.  The trace's x(t) increases with t
+ * on [-1, 1]; the t where x(t) = e is found by bisection (to the last bit).
+ */
+static double t_at_x(const orc_scene *s, int tr, double e)
+{
+    const double *cx = s->cx + ORC_NCOEF * tr;
+    int dx = s->deg_x[tr];
+    double lo = -1.0, hi = 1.0;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (horner(cx, dx, mid) < e) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/*
+ * Box extraction of every trace: for pixel column i whose edges i -+ 1/2
+ * both fall inside the trace's x range, the trace centre y_c = y(t) at
+ * x(t) = i and
+ *   E[tr][i] = sum_j |[j - 1/2, j + 1/2) n [y_c - A, y_c + A]| F[j][i]
+ * over the detector rows j; other columns get 0.  L[tr][e] (e = 0 .. nx)
+ * is the wavelength at the column edge x = e - 1/2, NaN outside the trace.
+ */
+void orc_extract(const orc_scene *s, const double *F, double A, double *E, double *L)
+{
+    const int nx = s->nx, ny = s->ny;
+    for (int tr = 0; tr < s->n_traces; ++tr) {
+        const double *cx = s->cx + ORC_NCOEF * tr, *cy = s->cy + ORC_NCOEF * tr;
+        double x0 = horner(cx, s->deg_x[tr], -1.0), x1 = horner(cx, s->deg_x[tr], 1.0);
+        double span = s->lmax[tr] - s->lmin[tr];
+        for (int e = 0; e <= nx; ++e) {
+            double xe = (double)e - 0.5;
+            double v = NAN;
+            if (xe >= x0 && xe <= x1) {
+                double t = t_at_x(s, tr, xe);
+                v = 0.5 * (t * span + s->lmin[tr] + s->lmax[tr]);
+            }
+            L[(size_t)tr * (nx + 1) + e] = v;
+        }
+        for (int i = 0; i < nx; ++i) {
+            double acc = 0.0;
+            if (!isnan(L[(size_t)tr * (nx + 1) + i]) && !isnan(L[(size_t)tr * (nx + 1) + i + 1])) {
+                double yc = horner(cy, s->deg_y[tr], t_at_x(s, tr, (double)i));
+                for (int j = 0; j < ny; ++j) {
+                    double ov = overlap((double)j - 0.5, (double)j + 0.5, yc - A, yc + A);
+                    if (ov > 0.0) acc += ov * F[(size_t)j * nx + i];
+                }
+            }
+            E[(size_t)tr * nx + i] = acc;
+        }
+    }
+}
+
+/* Moving mean of odd width w over x[0..n-1] (the window clipped to the
+ * array, divided by the samples it holds). */
+static void box_mean(const double *x, int64_t n, int w, double *y)
+{
+    int64_t h = w / 2;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t a = i - h < 0 ? 0 : i - h, b = i + h + 1 > n ? n : i + h + 1;
+        double acc = 0.0;
+        for (int64_t m = a; m < b; ++m) acc += x[m];
+        y[i] = acc / (double)(b - a);
+    }
+}
+
+/* Template smoothing: three passes of the moving mean of width w (their
+ * cascade approximates a Gaussian of variance 3 (w^2 - 1) / 12 samples^2;
+ * Wells, IEEE PAMI 8, 1986). */
+void orc_smooth3(const double *x, int64_t n, int w, double *y)
+{
+    double *t = (double *)malloc(sizeof(double) * (size_t)n);
+    box_mean(x, n, w, y);
+    box_mean(y, n, w, t);
+    box_mean(t, n, w, y);
+    free(t);
+}
+
+/* Odd moving-mean width whose three-pass cascade has a standard deviation
+ * of sigma_px pixels on a trace with n samples over its x span. */
+static int smooth_width(const orc_scene *s, int tr, double sigma_px)
+{
+    const double *cx = s->cx + ORC_NCOEF * tr;
+    double span_px = horner(cx, s->deg_x[tr], 1.0) - horner(cx, s->deg_x[tr], -1.0);
+    double sg = sigma_px * (double)s->n[tr] / span_px;
+    int w = (int)floor(sqrt(4.0 * sg * sg + 1.0) + 0.5);
+    if (w % 2 == 0) w += 1;
+    return w < 1 ? 1 : w;
+}
+
+/*
+ * Cross-correlation of the extracted spectra with the input spectra (Sec.
+ * 4.2: RV recovered by cross-correlation of the extracted 1-D spectrum).
+ * The template of a trace is its own spectrum slot (photons per sample on
+ * the cell-centred rest-frame grid lambda_m = lmin + (m + 1/2) dl) smoothed
+ * by orc_smooth3 to about the instrument's resolution (sigma_px pixels),
+ * so that lines narrower than a pixel do not alias with the pixel grid.
+ * The extracted flux is first divided by the extraction of a flat-field
+ * frame when one is given (Ef), which removes the blaze and dispersion
+ * trend along the order.  For trial velocity v_k = v0 + k dv (beta_k =
+ * v_k / c), column i with centre wavelength lc_i = (L_i + L_{i+1}) / 2
+ * sees the template at the fractional sample u_ik = (lc_i / (1 + beta_k) -
+ * lmin) / dl - 1/2, linearly interpolated.  The columns used have both
+ * edges on the trace, a positive flat (if given) and u_ik within
+ * [6h, n - 2 - 6h] (h = (w - 1) / 2) for every trial velocity: twice the
+ * smoothing support away from the ends of the trace, where the flux of a
+ * column depends on how far the Doppler shift moved the sampled range; with
+ * e_i = E_i (/ Ef_i) and e' = e - mean(e) over them,
+ *   C[tr][k] = sum_i e'_i S(u_ik).
+ * The velocity estimate is the vertex of the parabola through the largest
+ * value of sum_tr C[tr][k] (k in 1 .. nv-2) and its two neighbours.
+ */
+double orc_ccf(const orc_scene *s, const double *E, const double *Ef, const double *L, double v0,
+               double dv, int nv, double sigma_px, double *C)
+{
+    const int nx = s->nx;
+    double *tot = (double *)calloc((size_t)nv, sizeof(double));
+    double bmin = fmin(v0, v0 + (nv - 1) * dv) / C_LIGHT;
+    double bmax = fmax(v0, v0 + (nv - 1) * dv) / C_LIGHT;
+    for (int tr = 0; tr < s->n_traces; ++tr) {
+        const double *T = s->spec + s->spec_off[s->slot[tr]];
+        double lmin = s->lmin[tr], lmax = s->lmax[tr];
+        int64_t n = s->n[tr];
+        double dl = (lmax - lmin) / (double)n;
+        int w = smooth_width(s, tr, sigma_px), h = w / 2;
+        double *S = (double *)malloc(sizeof(double) * (size_t)n);
+        orc_smooth3(T, n, w, S);
+        const double *Lt = L + (size_t)tr * (nx + 1);
+        const double *Et = E + (size_t)tr * nx;
+        const double *Ft = Ef ? Ef + (size_t)tr * nx : NULL;
+        double ulo = 6.0 * h, uhi = (double)(n - 2 - 6 * h);
+#define ORC_LC(i) (0.5 * (Lt[i] + Lt[(i) + 1]))
+#define ORC_CCF_USE(i) (!isnan(Lt[i]) && !isnan(Lt[(i) + 1]) && (!Ft || Ft[i] > 0.0) && \
+                        (ORC_LC(i) / (1.0 + bmax) - lmin) / dl - 0.5 >= ulo && \
+                        (ORC_LC(i) / (1.0 + bmin) - lmin) / dl - 0.5 <= uhi)
+        double mean = 0.0;
+        int cnt = 0;
+        for (int i = 0; i < nx; ++i) {
+            if (!ORC_CCF_USE(i)) continue;
+            mean += Ft ? Et[i] / Ft[i] : Et[i];
+            ++cnt;
+        }
+        if (cnt > 0) mean /= cnt;
+        for (int k = 0; k < nv; ++k) {
+            double beta = (v0 + k * dv) / C_LIGHT, acc = 0.0;
+            for (int i = 0; i < nx; ++i) {
+                if (!ORC_CCF_USE(i)) continue;
+                double u = (ORC_LC(i) / (1.0 + beta) - lmin) / dl - 0.5;
+                int64_t m = (int64_t)floor(u);
+                double f = u - (double)m;
+                double tv = S[m] * (1.0 - f) + S[m + 1] * f;
+                double e = Ft ? Et[i] / Ft[i] : Et[i];
+                acc += (e - mean) * tv;
+            }
+            C[(size_t)tr * nv + k] = acc;
+            tot[k] += acc;
+        }
+#undef ORC_CCF_USE
+#undef ORC_LC
+        free(S);
+    }
+    int kb = 1;
+    for (int k = 1; k < nv - 1; ++k)
+        if (tot[k] > tot[kb]) kb = k;
+    double ym = tot[kb - 1], y0 = tot[kb], yp = tot[kb + 1];
+    double den = ym - 2.0 * y0 + yp;
+    double off = den != 0.0 ? 0.5 * (ym - yp) / den : 0.0;
+    free(tot);
+    return v0 + dv * ((double)kb + off);
+}

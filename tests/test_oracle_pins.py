@@ -667,3 +667,89 @@ def test_sfi_frame_flux_and_centroid():
         cy = (w.sum(1) * (j0 + np.arange(w.shape[0]))).sum()
         assert abs(cy - y - 4 * 1.2 / (3 * np.pi)) < 1e-6, cy - y
         assert abs(cx - x) < 1e-6
+
+
+# ------------------------------------------------- extraction and the CCF
+# Closing the loop from the frame back to a 1-D spectrum and an RV (Sec. 1,
+# Sec. 4.2).
+
+def test_extract_flat_frame_is_aperture_length():
+    """X1: on a uniform frame each column on the trace extracts exactly the
+    aperture length 2A (fractional end rows included); columns off the
+    trace extract nothing."""
+    sc = one_trace_scene([64.0, 50.0, 3.0, -2.0], [32.0, 4.0, 1.5], nx=128, ny=64)
+    for A in (2.3, 4.5, 6.0):
+        E, L = oracle.extract(sc, np.ones((64, 128)), A)
+        on = ~np.isnan(L[0, :-1]) & ~np.isnan(L[0, 1:])
+        assert np.all(np.abs(E[0][on] - 2 * A) < 1e-12)
+        assert np.all(E[0][~on] == 0.0)
+        x0, x1 = 64.0 - 50.0 + 3.0 + 2.0, 64.0 + 50.0 + 3.0 - 2.0   # x(-1), x(1)
+        assert on.sum() == int(np.floor(x1 - 0.5) - np.ceil(x0 + 0.5) + 1)
+
+
+def test_extract_wide_aperture_is_column_sum():
+    """X2: an aperture wider than the PSF window collects the whole column
+    of an isolated trace's rendered frame."""
+    psf = Psf(kind="erf", sigma=1.1, half_width=4)
+    sc = one_trace_scene([64.0, 40.0], [30.0, 1.0], n=3000, nx=128, ny=64, psf=psf)
+    F = oracle.render(sc)
+    E, L = oracle.extract(sc, F, 9.0)
+    on = ~np.isnan(L[0, :-1]) & ~np.isnan(L[0, 1:])
+    cs = F.sum(0)
+    assert np.max(np.abs(E[0][on] - cs[on])) < 1e-9 * cs.max()
+
+
+def test_extract_edges_linear_format():
+    """X3: for x(t) = c0 + c1 t the column edge e - 1/2 sits at
+    t = (e - 1/2 - c0) / c1, i.e. wavelength (t span + lmin + lmax) / 2."""
+    c0, c1 = 60.3, 41.7
+    sc = one_trace_scene([c0, c1], [30.0], nx=128, ny=64)
+    _, L = oracle.extract(sc, np.zeros((64, 128)), 3.0)
+    e = np.arange(129) - 0.5
+    t = (e - c0) / c1
+    want = np.where(np.abs(t) <= 1, (t * 5.0 + 1005.0) / 2, np.nan)
+    ok = ~np.isnan(want)
+    assert np.array_equal(ok, ~np.isnan(L[0]))
+    assert np.max(np.abs(L[0][ok] - want[ok])) < 1e-12
+
+
+def test_smooth3_matches_uniform_filter_and_moments():
+    """X4: three clipped moving means = scipy's uniform filter applied three
+    times away from the ends; constants stay; a unit impulse spreads into a
+    symmetric kernel of sum 1 and variance 3 (w^2 - 1) / 12."""
+    from scipy import ndimage
+    rng = np.random.default_rng(8)
+    x = rng.uniform(0, 1, 600)
+    for w in (1, 5, 31):
+        y = oracle.smooth3(x, w)
+        r = ndimage.uniform_filter1d(ndimage.uniform_filter1d(ndimage.uniform_filter1d(x, w), w), w)
+        h = 3 * (w // 2)
+        assert np.max(np.abs(y[h:600 - h] - r[h:600 - h])) < 1e-13
+        assert np.max(np.abs(oracle.smooth3(np.full(50, 2.5), w) - 2.5)) < 1e-14
+        d = np.zeros(301); d[150] = 1.0
+        k = oracle.smooth3(d, w)
+        m = np.arange(301) - 150
+        assert abs(k.sum() - 1) < 1e-14 and np.allclose(k, k[::-1], atol=1e-17)
+        assert abs((k * m * m).sum() - 3 * (w * w - 1) / 12) < 1e-10
+
+
+@pytest.mark.parametrize("name,A,vrange", [("c0", 6.5, 30000.0), ("mini_table", 4.5, 20000.0)])
+def test_rv_round_trip(name, A, vrange):
+    """X5: render a frame at a known radial velocity, extract it, divide by
+    the extracted flat (same scene, constant spectra) and cross-correlate
+    with the input spectra: the CCF vertex recovers the velocity to a small
+    fraction of a pixel (these scenes have 6-8 km/s per pixel)."""
+    sc = scene(name)
+    fl = dataclasses.replace(sc, spectra=[np.full_like(s, 1e4) for s in sc.spectra])
+    Ef, _ = oracle.extract(fl, oracle.render(fl), A)
+    nv = int(2 * vrange / 500.0) + 1
+    for v0 in (2000.0, -3333.0):
+        E, L = oracle.extract(sc, oracle.render(sc, Request(rv_mps=v0)), A)
+        C, rv = oracle.ccf(sc, E, L, -vrange, 500.0, nv, flat=Ef, smooth_px=1.5)
+        assert abs(rv - v0) < 40.0, (name, v0, rv)
+        # every stellar trace's own CCF peaks within one step of the
+        # velocity (a Fabry-Perot comb correlates at its free spectral range
+        # too)
+        star = [i for i, t in enumerate(sc.traces) if t.fiber == 0]
+        pk = -vrange + 500.0 * np.argmax(C[star], axis=1)
+        assert np.all(np.abs(pk - v0) <= 750.0)
