@@ -234,6 +234,46 @@ def secondary(E, P, torch, ctx, sc1, ld1, specs1, log):
     res["detector_c1"] = det
     del out1, g1, adu
 
+    log("secondary: c1 extraction + CCF (closing the loop)")
+    import ctypes as C
+    import dataclasses as dc
+    out1 = torch.empty((sc1.ny, sc1.nx), dtype=torch.float32, device="cuda")
+    flat1 = dc.replace(sc1, spectra=[np.full_like(s_, 1e4) for s_ in sc1.spectra])
+    ldf = P.Loaded(ctx, flat1)
+    spf = [torch.from_numpy(s_).to("cuda") for s_ in flat1.spectra]
+    r, k = P.make_req(ldf, [s_.data_ptr() for s_ in spf], E.E2E_F32, out1.data_ptr(), E.E2E_F32,
+                      spectra_on_device=True, out_on_device=True)
+    E.e2e_render(ctx, r)
+    ntr = len(sc1.traces)
+    flux = torch.empty((ntr, sc1.nx), dtype=torch.float64, device="cuda")
+    flatx = torch.empty_like(flux)
+    edges = torch.empty((ntr, sc1.nx + 1), dtype=torch.float64, device="cuda")
+    E.e2e_extract(ctx, ld1.fmt, out1.data_ptr(), E.E2E_F32, 4.5, flatx.data_ptr(),
+                  edges.data_ptr(), 1)
+    v_in = 1234.5
+    r, k = P.make_req(ld1, [s_.data_ptr() for s_ in specs1], E.E2E_F32, out1.data_ptr(),
+                      E.E2E_F32, spectra_on_device=True, out_on_device=True, rv_mps=v_in)
+    E.e2e_render(ctx, r)
+    tm = (C.c_void_p * len(specs1))(*[s_.data_ptr() for s_ in specs1])
+    cc = torch.empty((ntr, 101), dtype=torch.float64, device="cuda")
+    creq = E.e2e_ccf_req(flux.data_ptr(), flatx.data_ptr(), edges.data_ptr(), tm, len(specs1),
+                         E.E2E_F32, 1, 101, -5000.0, 100.0, 1.5, cc.data_ptr(), None)
+    rv_box = []
+
+    def loop():
+        E.e2e_extract(ctx, ld1.fmt, out1.data_ptr(), E.E2E_F32, 4.5, flux.data_ptr(),
+                      edges.data_ptr(), 1)
+        rv_box.append(E.e2e_ccf(ctx, ld1.fmt, creq))
+    ms_x = kernel_ms(loop, "extract")
+    ms_s = kernel_ms(loop, "template_smooth")
+    ms_c = kernel_ms(loop, "ccf")
+    res["loop_c1"] = {"extract_ms": ms_x, "template_smooth_ms_per_group": ms_s,
+                      "template_smooth_ms": ms_s * ((ntr + 63) // 64), "ccf_ms_per_group": ms_c,
+                      "ccf_ms": ms_c * ((ntr + 63) // 64), "traces": ntr, "n_v": 101,
+                      "rv_injected_mps": v_in, "rv_recovered_mps": rv_box[-1]}
+    ldf.free()
+    del spf, flux, flatx, edges, cc, out1
+
     log("secondary: c4 HIRES-shaped frame")
     c4 = scene("c4")
     ld4 = P.Loaded(ctx, c4)

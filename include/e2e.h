@@ -316,6 +316,70 @@ e2e_status e2e_detector(e2e_ctx *ctx, const e2e_detector_desc *d, const void *fr
                         uint16_t *adu_out, int32_t on_device, void *hip_stream);
 
 /*
+ * Closing the loop (Sec. 1: the simulated frames feed a data-reduction
+ * pipeline; Sec. 4.2: 1-D spectra extracted along the traced orders, a
+ * wavelength scale from the dispersion, the radial velocity recovered by
+ * cross-correlation).
+ *
+ * e2e_extract: box extraction of every trace of format `fmt` from a frame
+ * [ny][nx] of frame_dtype.  For pixel column i whose edges i -+ 1/2 both
+ * lie inside the trace's x range [x(-1), x(1)], with t_c the format
+ * coordinate where x(t_c) = i and y_c = y(t_c):
+ *   flux[tr][i] = sum_j |[j - 1/2, j + 1/2) n [y_c - A, y_c + A]| F[j][i]
+ * over the detector rows (A = aperture_half_px > 0), and 0 for the other
+ * columns; edges[tr][e] (e = 0 .. nx) is the detector-frame wavelength
+ * (t (lmax - lmin) + lmin + lmax) / 2 at x(t) = e - 1/2, NaN off the trace.
+ * flux is [ntr][nx] FP64, edges [ntr][nx+1] FP64.  on_device = 1: all
+ * three arrays are device pointers and the work is ordered on hip_stream
+ * (NULL: the context's stream); 0: host arrays, staged.  Returns when done.
+ * Errors: E2E_EINVAL (NULL pointers, bad dtype, A <= 0 or not finite),
+ * E2E_ENOTFOUND (fmt), E2E_ENOMEM, E2E_EDEVICE.
+ */
+e2e_status e2e_extract(e2e_ctx *ctx, e2e_format_id fmt, const void *frame, int32_t frame_dtype,
+                       double aperture_half_px, double *flux, double *edges, int32_t on_device,
+                       void *hip_stream);
+
+/*
+ * e2e_ccf: cross-correlation of extracted spectra with the input spectra.
+ * The template of trace tr is its spectrum slot (photons per sample on the
+ * rest-frame grid lambda_m = lmin + (m + 1/2) dl, dl = (lmax - lmin) / n)
+ * smoothed by three passes of a moving mean of odd width w (clipped at the
+ * ends; w = the odd integer nearest sqrt(4 s^2 + 1), s = smooth_px n /
+ * (x(1) - x(-1)), so the cascade's standard deviation is about smooth_px
+ * pixels), which keeps lines narrower than a pixel from aliasing with the
+ * pixel grid.  With e_i = flux_i / flat_i (flux_i if flat is NULL), trial
+ * velocities v_k = v0 + k dv (k < n_v, beta_k = v_k / c) and the column
+ * centre wavelength lc_i = (edges_i + edges_{i+1}) / 2, the template is read
+ * at the fractional sample u_ik = (lc_i / (1 + beta_k) - lmin) / dl - 1/2
+ * by linear interpolation.  Columns used: both edges finite, flat_i > 0 (if
+ * given), u_ik in [6h, n - 2 - 6h] (h = (w - 1) / 2) for every k; with
+ * e' = e - mean(e) over them, ccf[tr][k] = sum_i e'_i S(u_ik).  *rv_mps_out
+ * receives the vertex of the parabola through the largest value of
+ * sum_tr ccf[tr][k] (k in 1 .. n_v - 2) and its two neighbours.
+ * on_device: flux / flat / edges / templates / ccf_out are device pointers
+ * (templates is still a host array of n_templates pointers).  ccf_out may
+ * be NULL.  The library allocates the smoothed templates of up to 64
+ * traces at a time (3 n FP64 values per trace) for the call.
+ * Errors: E2E_EINVAL (NULL pointers, n_v < 3, dv = 0, smooth_px <= 0,
+ * too few templates, bad dtype), E2E_ENOTFOUND, E2E_ENOMEM, E2E_EDEVICE.
+ */
+typedef struct {
+    const double *flux;            /* [ntr][nx]                                */
+    const double *flat;            /* [ntr][nx] or NULL                        */
+    const double *edges;           /* [ntr][nx+1]                              */
+    const void *const *templates;  /* per spectrum slot                        */
+    int32_t n_templates;
+    int32_t template_dtype;        /* E2E_F32 / E2E_F64                        */
+    int32_t on_device;
+    int32_t n_v;
+    double v0_mps, dv_mps;
+    double smooth_px;
+    double *ccf_out;               /* [ntr][n_v] or NULL                       */
+    void *hip_stream;
+} e2e_ccf_req;
+e2e_status e2e_ccf(e2e_ctx *ctx, e2e_format_id fmt, const e2e_ccf_req *req, double *rv_mps_out);
+
+/*
  * Raw Philox-4x32-10 blocks (Salmon et al., SC'11) of the noise stream:
  * out_host[(p * blocks + b) * 4 + w] = word w of block b of pixel pixel0+p.
  */
@@ -328,7 +392,7 @@ e2e_status e2e_philox_blocks(e2e_ctx *ctx, uint64_t seed, uint32_t frame_index,
  * render kernels with HIP events on the launch stream.  e2e_kernel_time
  * returns launches and total milliseconds per kernel name ("render_table",
  * "render_sep", "render_sep_mfma", "render_sfi", "plan", "noise",
- * "detector"), synchronising first.
+ * "detector", "extract", "template_smooth", "ccf"), synchronising first.
  */
 e2e_status e2e_set_profiling(e2e_ctx *ctx, int32_t on);
 e2e_status e2e_kernel_time(e2e_ctx *ctx, const char *kernel, int64_t *launches,

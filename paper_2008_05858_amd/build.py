@@ -9,7 +9,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libe2e.so")
 SOURCES = ["api.cpp", "serve.cpp", "k_plan.hip", "k_table.hip", "k_sep.hip",
-           "k_sep_mfma.hip", "k_noise.hip", "k_detector.hip", "k_sfi.hip"]
+           "k_sep_mfma.hip", "k_noise.hip", "k_detector.hip", "k_sfi.hip",
+           "k_loop.hip", "api_loop.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
          "-Wno-unused-function", "-Wno-unused-result", "-Wno-unused-value",

@@ -1,0 +1,296 @@
+// Closing the loop from the frame back to a radial velocity (Sec. 1: the
+// simulated frames feed a data-reduction pipeline; Sec. 4.2: 1-D spectra
+// extracted along the traced orders, the wavelength scale from the
+// dispersion, the RV recovered by cross-correlation).
+//
+//  * k_extract: one thread per (trace, pixel column edge): the format
+//    coordinate of the edge and of the column centre by safeguarded Newton
+//    on x(t) (FP64), the edge wavelength, and the column's box extraction
+//    over the rows within +-A of the trace centre (fractional end rows).
+//    Neighbouring lanes read neighbouring pixels of each row.
+//  * k_smooth3: one workgroup per trace: three passes of a clipped moving
+//    mean over the template (the input spectrum of the trace), each an FP64
+//    prefix sum (256 threads x 8 consecutive samples per step, coalesced)
+//    followed by window differences.
+//  * k_ccf: one workgroup per (trace, 8 trial velocities): the mean of the
+//    flat-divided flux over the usable columns, then per column and
+//    velocity the template read at the Doppler-shifted column centre by
+//    linear interpolation; fixed-order block sums.
+#include "dev_common.h"
+
+namespace e2e {
+
+namespace {
+
+// Format coordinate t in [-1, 1] with x(t) = xe, x increasing on [-1, 1]
+// (xa = x(-1) <= xe <= xb = x(1)): Newton steps from the linear guess,
+// kept inside the shrinking bracket (bisection when a step would leave it).
+__device__ double t_at_x(const double *cx, double xe, double xa, double xb)
+{
+    double lo = -1.0, hi = 1.0;
+    double t = xb > xa ? fma(2.0, (xe - xa) / (xb - xa), -1.0) : 0.0;
+    t = fmin(fmax(t, lo), hi);
+    for (int it = 0; it < 64; ++it) {
+        double d;
+        const double f = horner_d<kNCoef - 1>(cx, t, &d) - xe;
+        if (f == 0.0) break;
+        if (f < 0.0) lo = t;
+        else hi = t;
+        double tn = d > 0.0 ? t - f / d : 0.5 * (lo + hi);
+        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+        if (tn == t || hi - lo <= 0.0) break;
+        t = tn;
+    }
+    return t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_extract(const TraceDev *__restrict__ trs, int nx, int ny,
+                                                 const T *__restrict__ frame, double A,
+                                                 double *__restrict__ flux,
+                                                 double *__restrict__ edges)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x, tr = blockIdx.y;
+    if (e > nx) return;
+    const TraceDev &Tr = trs[tr];
+    const double xa = horner<kNCoef - 1>(Tr.cx, -1.0), xb = horner<kNCoef - 1>(Tr.cx, 1.0);
+    const double span = Tr.lmax - Tr.lmin;
+    const double xe = (double)e - 0.5;
+    double lam = __builtin_nan("");
+    if (xe >= xa && xe <= xb) {
+        const double t = t_at_x(Tr.cx, xe, xa, xb);
+        lam = 0.5 * fma(t, span, Tr.lmin + Tr.lmax);
+    }
+    edges[(size_t)tr * (nx + 1) + e] = lam;
+    if (e == nx) return;
+    const int i = e;
+    double acc = 0.0;
+    if ((double)i - 0.5 >= xa && (double)i + 0.5 <= xb) {
+        const double yc = horner<kNCoef - 1>(Tr.cy, t_at_x(Tr.cx, (double)i, xa, xb));
+        const double lo = yc - A, hi = yc + A;
+        const int j0 = max(0, (int)floor(lo + 0.5)), j1 = min(ny - 1, (int)floor(hi + 0.5));
+        for (int j = j0; j <= j1; ++j) {
+            const double ov = fmin((double)j + 0.5, hi) - fmax((double)j - 0.5, lo);
+            if (ov > 0.0) acc = fma(ov, (double)frame[(size_t)j * nx + i], acc);
+        }
+    }
+    flux[(size_t)tr * nx + i] = acc;
+}
+
+// Per-trace parameters of the template smoothing and the CCF.
+struct LoopTrace {
+    const void *tmpl;   // template (spectrum slot), FP32 or FP64
+    double *P;          // prefix sums, n + 1
+    double *X;          // smoothed template, n
+    int64_t n;
+    int32_t w;          // moving-mean width (odd)
+    int32_t pad;
+};
+
+// Exclusive block scan of 256 per-thread totals (FP64, fixed order).
+__device__ double block_exclusive(double v, double *sh, double *total)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) sh[wv] = x;
+    __syncthreads();
+    double base = 0.0;
+    for (int q = 0; q < wv; ++q) base += sh[q];
+    *total = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    __syncthreads();
+    return base + x - v;
+}
+
+template <typename TT>
+__device__ void prefix_pass(const TT *__restrict__ x, double *__restrict__ P, int64_t n,
+                            double *sh)
+{
+    const int tid = threadIdx.x;
+    double carry = 0.0;
+    if (tid == 0) P[0] = 0.0;
+    for (int64_t base = 0; base < n; base += 2048) {
+        double v[8], s = 0.0;
+        const int64_t b = base + 8 * tid;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            v[r] = b + r < n ? (double)x[b + r] : 0.0;
+            s += v[r];
+        }
+        double tot;
+        double run = carry + block_exclusive(s, sh, &tot);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            run += v[r];
+            if (b + r < n) P[b + r + 1] = run;
+        }
+        carry += tot;
+    }
+}
+
+__device__ void box_pass(const double *__restrict__ P, double *__restrict__ X, int64_t n, int w)
+{
+    const int64_t h = w / 2;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const int64_t a = i - h < 0 ? 0 : i - h, b = i + h + 1 > n ? n : i + h + 1;
+        X[i] = (P[b] - P[a]) / (double)(b - a);
+    }
+}
+
+template <typename TT>
+__global__ __launch_bounds__(256) void k_smooth3(const LoopTrace *__restrict__ lt)
+{
+    __shared__ double sh[4];
+    const LoopTrace L = lt[blockIdx.x];
+    prefix_pass((const TT *)L.tmpl, L.P, L.n, sh);
+    __syncthreads();
+    box_pass(L.P, L.X, L.n, L.w);
+    for (int pass = 1; pass < 3; ++pass) {
+        __syncthreads();
+        prefix_pass((const double *)L.X, L.P, L.n, sh);
+        __syncthreads();
+        box_pass(L.P, L.X, L.n, L.w);
+    }
+}
+
+constexpr int KV = 8;   // trial velocities per workgroup
+
+__global__ __launch_bounds__(256) void k_ccf(const TraceDev *__restrict__ trs, int tr0,
+                                             const LoopTrace *__restrict__ lt, int nx,
+                                             const double *__restrict__ flux,
+                                             const double *__restrict__ flat,
+                                             const double *__restrict__ edges, double v0,
+                                             double dv, int nv, double *__restrict__ C)
+{
+    __shared__ double red[KV][256];
+    __shared__ double sh_mean;
+    const int tid = threadIdx.x, g = blockIdx.y, tr = tr0 + g, k0 = blockIdx.x * KV;
+    const TraceDev &Tr = trs[tr];
+    const LoopTrace L = lt[g];
+    const double c = 299792458.0;
+    const double vlo = fmin(v0, v0 + (nv - 1) * dv), vhi = fmax(v0, v0 + (nv - 1) * dv);
+    const double bmin = vlo / c, bmax = vhi / c;
+    const double dl = (Tr.lmax - Tr.lmin) / (double)L.n;
+    const int h = L.w / 2;
+    const double ulo = 6.0 * h, uhi = (double)(L.n - 2 - 6 * h);
+    const double *Ft = flux + (size_t)tr * nx, *Lt = edges + (size_t)tr * (nx + 1);
+    const double *Ff = flat ? flat + (size_t)tr * nx : nullptr;
+    auto usable = [&](int i, double *lc) {
+        const double a = Lt[i], b = Lt[i + 1];
+        if (isnan(a) || isnan(b)) return false;
+        if (Ff && !(Ff[i] > 0.0)) return false;
+        *lc = 0.5 * (a + b);
+        return (*lc / (1.0 + bmax) - Tr.lmin) / dl - 0.5 >= ulo &&
+               (*lc / (1.0 + bmin) - Tr.lmin) / dl - 0.5 <= uhi;
+    };
+    // mean of e over the usable columns
+    double s = 0.0, cnt = 0.0;
+    for (int i = tid; i < nx; i += 256) {
+        double lc;
+        if (usable(i, &lc)) {
+            s += Ff ? Ft[i] / Ff[i] : Ft[i];
+            cnt += 1.0;
+        }
+    }
+    red[0][tid] = s;
+    red[1][tid] = cnt;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) {
+            red[0][tid] += red[0][tid + o];
+            red[1][tid] += red[1][tid + o];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) sh_mean = red[1][0] > 0.0 ? red[0][0] / red[1][0] : 0.0;
+    __syncthreads();
+    const double mean = sh_mean;
+    double acc[KV];
+#pragma unroll
+    for (int q = 0; q < KV; ++q) acc[q] = 0.0;
+    for (int i = tid; i < nx; i += 256) {
+        double lc;
+        if (!usable(i, &lc)) continue;
+        const double e = (Ff ? Ft[i] / Ff[i] : Ft[i]) - mean;
+#pragma unroll
+        for (int q = 0; q < KV; ++q) {
+            const int k = k0 + q;
+            if (k >= nv) break;
+            const double beta = (v0 + k * dv) / c;
+            const double u = (lc / (1.0 + beta) - Tr.lmin) / dl - 0.5;
+            const int64_t m = (int64_t)floor(u);
+            const double f = u - (double)m;
+            acc[q] = fma(e, fma(L.X[m + 1] - L.X[m], f, L.X[m]), acc[q]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < KV; ++q) red[q][tid] = acc[q];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o)
+#pragma unroll
+            for (int q = 0; q < KV; ++q) red[q][tid] += red[q][tid + o];
+        __syncthreads();
+    }
+    if (tid < KV && k0 + tid < nv) C[(size_t)tr * nv + k0 + tid] = red[tid][0];
+}
+
+}  // namespace
+
+hipError_t launch_extract(const TraceDev *trs, int ntr, int nx, int ny, const void *frame,
+                          int f64, double A, double *flux, double *edges, hipStream_t s)
+{
+    if (ntr <= 0 || nx <= 0) return hipSuccess;
+    const dim3 grid((nx + 1 + 255) / 256, ntr);
+    if (f64)
+        hipLaunchKernelGGL(k_extract<double>, grid, dim3(256), 0, s, trs, nx, ny,
+                           (const double *)frame, A, flux, edges);
+    else
+        hipLaunchKernelGGL(k_extract<float>, grid, dim3(256), 0, s, trs, nx, ny,
+                           (const float *)frame, A, flux, edges);
+    return hipGetLastError();
+}
+
+hipError_t launch_smooth3(const void *lt_dev, int ntr, int f64, hipStream_t s)
+{
+    if (ntr <= 0) return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL(k_smooth3<double>, dim3(ntr), dim3(256), 0, s,
+                           (const LoopTrace *)lt_dev);
+    else
+        hipLaunchKernelGGL(k_smooth3<float>, dim3(ntr), dim3(256), 0, s,
+                           (const LoopTrace *)lt_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_ccf(const TraceDev *trs, int tr0, int ntr, const void *lt_dev, int nx,
+                      const double *flux, const double *flat, const double *edges, double v0,
+                      double dv, int nv, double *C, hipStream_t s)
+{
+    if (ntr <= 0) return hipSuccess;
+    const dim3 grid((nv + KV - 1) / KV, ntr);
+    hipLaunchKernelGGL(k_ccf, grid, dim3(256), 0, s, trs, tr0, (const LoopTrace *)lt_dev, nx,
+                       flux, flat, edges, v0, dv, nv, C);
+    return hipGetLastError();
+}
+
+size_t loop_trace_bytes() { return sizeof(LoopTrace); }
+
+void loop_trace_fill(void *dst, const void *tmpl, double *P, double *X, int64_t n, int w)
+{
+    LoopTrace L;
+    L.tmpl = tmpl;
+    L.P = P;
+    L.X = X;
+    L.n = n;
+    L.w = w;
+    L.pad = 0;
+    *(LoopTrace *)dst = L;
+}
+
+}  // namespace e2e

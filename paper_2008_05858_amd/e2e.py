@@ -31,7 +31,7 @@ EXPORTS = ["e2e_create", "e2e_destroy", "e2e_last_error", "e2e_version", "e2e_fo
            "e2e_psf_load", "e2e_format_free", "e2e_psf_free", "e2e_render", "e2e_render_batch",
            "e2e_serve_start", "e2e_serve_submit", "e2e_serve_poll", "e2e_serve_stop",
            "e2e_noise_poisson", "e2e_philox_blocks", "e2e_set_profiling", "e2e_kernel_time",
-           "e2e_reset_kernel_time", "e2e_autotune", "e2e_detector"]
+           "e2e_reset_kernel_time", "e2e_autotune", "e2e_detector", "e2e_extract", "e2e_ccf"]
 E2E_TUNE_MAX = 16
 
 
@@ -76,6 +76,14 @@ class e2e_detector_desc(C.Structure):
                 ("gain_e_per_adu", C.c_double), ("bias_adu", C.c_double),
                 ("seed", C.c_uint64), ("frame_index", C.c_uint32),
                 ("shot_noise", C.c_int32), ("bits", C.c_int32), ("reserved", C.c_int32)]
+
+
+class e2e_ccf_req(C.Structure):
+    _fields_ = [("flux", C.c_void_p), ("flat", C.c_void_p), ("edges", C.c_void_p),
+                ("templates", C.POINTER(C.c_void_p)), ("n_templates", C.c_int32),
+                ("template_dtype", C.c_int32), ("on_device", C.c_int32), ("n_v", C.c_int32),
+                ("v0_mps", C.c_double), ("dv_mps", C.c_double), ("smooth_px", C.c_double),
+                ("ccf_out", C.c_void_p), ("hip_stream", C.c_void_p)]
 
 
 class e2e_render_stats(C.Structure):
@@ -139,6 +147,9 @@ def lib():
         L.e2e_kernel_time.argtypes = [C.c_void_p, C.c_char_p, P(C.c_int64), P(C.c_double)]
         L.e2e_reset_kernel_time.argtypes = [C.c_void_p]
         L.e2e_autotune.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, P(e2e_tune_report)]
+        L.e2e_extract.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_int32, C.c_double,
+                                  C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
+        L.e2e_ccf.argtypes = [C.c_void_p, C.c_uint64, P(e2e_ccf_req), P(C.c_double)]
         L.e2e_detector.argtypes = [C.c_void_p, P(e2e_detector_desc), C.c_void_p, C.c_int32,
                                    C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
                                    C.c_void_p]
@@ -237,6 +248,20 @@ def e2e_detector(ctx, desc, frame_ptr, frame_dtype, prnu_ptr, nx, ny, adu_ptr, o
     ADC) of an nx x ny frame into uint16 ADU; pointers as in the C call."""
     return check(lib().e2e_detector(ctx, C.byref(desc), frame_ptr, frame_dtype, prnu_ptr, nx,
                                     ny, adu_ptr, on_device, stream))
+
+
+def e2e_extract(ctx, fmt, frame_ptr, frame_dtype, aperture_half_px, flux_ptr, edges_ptr,
+                on_device, stream=None):
+    """Box extraction of every trace: flux [ntr][nx], edge wavelengths [ntr][nx+1]."""
+    return check(lib().e2e_extract(ctx, fmt, frame_ptr, frame_dtype, aperture_half_px, flux_ptr,
+                                   edges_ptr, on_device, stream))
+
+
+def e2e_ccf(ctx, fmt, req):
+    """CCF of extracted spectra with the smoothed templates; returns the RV (m/s)."""
+    rv = C.c_double()
+    check(lib().e2e_ccf(ctx, fmt, C.byref(req), C.byref(rv)))
+    return rv.value
 
 
 def e2e_philox_blocks(ctx, seed, frame_index, pixel0, n_pixels, blocks):
