@@ -274,6 +274,33 @@ def secondary(E, P, torch, ctx, sc1, ld1, specs1, log):
     ldf.free()
     del spf, flux, flatx, edges, cc, out1
 
+    log("secondary: aliasing study (flat fields, wavelength step x sub-pixel sampling)")
+    from workloads.synth import aliasing_flat
+    from workloads.metrics import aliasing_level
+    cfg = [(p_, s_) for p_ in (1, 1.5, 2, 2.5, 3, 5, 10, 20) for s_ in (1, 2, 5, 10)]
+    scs = [aliasing_flat(p_, s_, length_px=1000.0) for p_, s_ in cfg]
+    lds = [P.Loaded(ctx, sc_) for sc_ in scs]
+    sps = [[torch.from_numpy(x_).to("cuda") for x_ in sc_.spectra] for sc_ in scs]
+    outs = [torch.empty((sc_.ny, sc_.nx), dtype=torch.float64, device="cuda") for sc_ in scs]
+    rqs, keep = [], []
+    for sc_, ld_, sp_, o_ in zip(scs, lds, sps, outs):
+        r_, k_ = P.make_req(ld_, [x_.data_ptr() for x_ in sp_], E.E2E_F32, o_.data_ptr(),
+                            E.E2E_F64, spectra_on_device=True, out_on_device=True)
+        rqs.append(r_)
+        keep.append(k_)
+    ms = kernel_ms(lambda: E.e2e_render_batch(ctx, rqs), "render_sfi")
+    table = {}
+    for (p_, s_), sc_, o_ in zip(cfg, scs, outs):
+        a_ = aliasing_level(o_.cpu().numpy(), sc_)
+        table[f"{p_}/{s_}"] = [a_["row_ripple"], a_["row_photon"]]
+    res["aliasing_sweep"] = {"frames": len(cfg), "batch_ms": ms,
+                             "sfi": int(sum(sc_.n_samples for sc_ in scs)),
+                             "key": "SFIs per resolution element / sub-pixels",
+                             "row_ripple_vs_photon": table}
+    for ld_ in lds:
+        ld_.free()
+    del sps, outs
+
     log("secondary: c4 HIRES-shaped frame")
     c4 = scene("c4")
     ld4 = P.Loaded(ctx, c4)

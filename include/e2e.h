@@ -359,9 +359,10 @@ e2e_status e2e_extract(e2e_ctx *ctx, e2e_format_id fmt, const void *frame, int32
  * on_device: flux / flat / edges / templates / ccf_out are device pointers
  * (templates is still a host array of n_templates pointers).  ccf_out may
  * be NULL.  The library allocates the smoothed templates of up to 64
- * traces at a time (3 n FP64 values per trace) for the call.
- * Errors: E2E_EINVAL (NULL pointers, n_v < 3, dv = 0, smooth_px <= 0,
- * too few templates, bad dtype), E2E_ENOTFOUND, E2E_ENOMEM, E2E_EDEVICE.
+ * traces at a time (2 n FP64 values per trace) for the call.
+ * Errors: E2E_EINVAL (NULL pointers, n_v < 3, dv = 0, smooth_px <= 0, a
+ * moving-mean width above 4095 samples, too few templates, bad dtype),
+ * E2E_ENOTFOUND, E2E_ENOMEM, E2E_EDEVICE.
  */
 typedef struct {
     const double *flux;            /* [ntr][nx]                                */

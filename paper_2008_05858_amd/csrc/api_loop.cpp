@@ -10,7 +10,8 @@
 namespace e2e {
 hipError_t launch_extract(const TraceDev *trs, int ntr, int nx, int ny, const void *frame,
                           int f64, double A, double *flux, double *edges, hipStream_t s);
-hipError_t launch_smooth3(const void *lt_dev, int ntr, int f64, hipStream_t s);
+hipError_t launch_smooth3(const void *lt_dev, int ntr, int64_t nmax, int f64, hipStream_t s);
+int loop_max_width();
 hipError_t launch_ccf(const TraceDev *trs, int tr0, int ntr, const void *lt_dev, int nx,
                       const double *flux, const double *flat, const double *edges, double v0,
                       double dv, int nv, double *C, hipStream_t s);
@@ -166,6 +167,9 @@ extern "C" e2e_status e2e_ccf(e2e_ctx *ctx, e2e_format_id fmt, const e2e_ccf_req
         int wi = (int)std::floor(std::sqrt(4.0 * sg * sg + 1.0) + 0.5);
         if (wi % 2 == 0) wi += 1;
         w[t] = std::max(1, wi);
+        if (w[t] > loop_max_width())
+            return fail(E2E_EINVAL, "e2e_ccf: smoothing window of trace %d is %d samples (max %d)",
+                        t, w[t], loop_max_width());
         nmax = std::max<int64_t>(nmax, T.n);
     }
     double *Cd;
@@ -196,7 +200,9 @@ extern "C" e2e_status e2e_ccf(e2e_ctx *ctx, e2e_format_id fmt, const e2e_ccf_req
         if ((e = hipMemcpyAsync(ltd, stage, g * ltb, hipMemcpyHostToDevice, s)) != hipSuccess)
             break;
         prof_begin(ctx, s, "template_smooth");
-        e = launch_smooth3(ltd, g, r->template_dtype == E2E_F64, s);
+        int64_t ng = 0;
+        for (int q = 0; q < g; ++q) ng = std::max<int64_t>(ng, F->host[t0 + q].n);
+        e = launch_smooth3(ltd, g, ng, r->template_dtype == E2E_F64, s);
         prof_end(ctx, s);
         if (e != hipSuccess) break;
         prof_begin(ctx, s, "ccf");

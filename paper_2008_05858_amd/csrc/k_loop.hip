@@ -8,10 +8,11 @@
 //    on x(t) (FP64), the edge wavelength, and the column's box extraction
 //    over the rows within +-A of the trace centre (fractional end rows).
 //    Neighbouring lanes read neighbouring pixels of each row.
-//  * k_smooth3: one workgroup per trace: three passes of a clipped moving
-//    mean over the template (the input spectrum of the trace), each an FP64
-//    prefix sum (256 threads x 8 consecutive samples per step, coalesced)
-//    followed by window differences.
+//  * k_box_pass (three launches): the three passes of a clipped moving
+//    mean over the template (the input spectrum of the trace); one
+//    workgroup per 2048 outputs of a trace stages its inputs and the
+//    half-windows around them in LDS, scans them (FP64) and takes window
+//    differences, so every pass reads and writes each sample about once.
 //  * k_ccf: one workgroup per (trace, 8 trial velocities): the mean of the
 //    flat-divided flux over the usable columns, then per column and
 //    velocity the template read at the Doppler-shifted column centre by
@@ -87,73 +88,50 @@ struct LoopTrace {
     int32_t pad;
 };
 
-// Exclusive block scan of 256 per-thread totals (FP64, fixed order).
-__device__ double block_exclusive(double v, double *sh, double *total)
-{
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    double x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const double y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) sh[wv] = x;
-    __syncthreads();
-    double base = 0.0;
-    for (int q = 0; q < wv; ++q) base += sh[q];
-    *total = ((sh[0] + sh[1]) + sh[2]) + sh[3];
-    __syncthreads();
-    return base + x - v;
-}
+constexpr int SMT = 2048;        // smoothed samples per workgroup
+constexpr int SMW = 4095;        // widest moving mean
 
+// One moving-mean pass over a tile of SMT outputs of one trace: the tile's
+// inputs with a half-window on each side are staged in LDS, scanned (FP64,
+// 256 threads x consecutive runs), and each output is the window sum (the
+// window clipped to the array) over its count.  Pass 0 reads the template
+// into X, pass 1 X into P, pass 2 P into X.
 template <typename TT>
-__device__ void prefix_pass(const TT *__restrict__ x, double *__restrict__ P, int64_t n,
-                            double *sh)
+__global__ __launch_bounds__(256) void k_box_pass(const LoopTrace *__restrict__ lt, int pass)
 {
+    __shared__ double q[SMT + SMW + 1];
+    __shared__ double tsum[256];
+    const LoopTrace L = lt[blockIdx.y];
+    const int64_t n = L.n, h = L.w / 2;
+    const int64_t t0 = (int64_t)blockIdx.x * SMT;
+    if (t0 >= n) return;
+    const int64_t t1 = t0 + SMT < n ? t0 + SMT : n;
+    const int64_t base = t0 - h > 0 ? t0 - h : 0, end = t1 + h < n ? t1 + h : n;
+    const int len = (int)(end - base);
+    const double *src = pass == 1 ? L.X : L.P;
+    double *dst = pass == 1 ? L.P : L.X;
     const int tid = threadIdx.x;
-    double carry = 0.0;
-    if (tid == 0) P[0] = 0.0;
-    for (int64_t base = 0; base < n; base += 2048) {
-        double v[8], s = 0.0;
-        const int64_t b = base + 8 * tid;
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            v[r] = b + r < n ? (double)x[b + r] : 0.0;
-            s += v[r];
-        }
-        double tot;
-        double run = carry + block_exclusive(s, sh, &tot);
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            run += v[r];
-            if (b + r < n) P[b + r + 1] = run;
-        }
-        carry += tot;
-    }
-}
-
-__device__ void box_pass(const double *__restrict__ P, double *__restrict__ X, int64_t n, int w)
-{
-    const int64_t h = w / 2;
-    for (int64_t i = threadIdx.x; i < n; i += 256) {
-        const int64_t a = i - h < 0 ? 0 : i - h, b = i + h + 1 > n ? n : i + h + 1;
-        X[i] = (P[b] - P[a]) / (double)(b - a);
-    }
-}
-
-template <typename TT>
-__global__ __launch_bounds__(256) void k_smooth3(const LoopTrace *__restrict__ lt)
-{
-    __shared__ double sh[4];
-    const LoopTrace L = lt[blockIdx.x];
-    prefix_pass((const TT *)L.tmpl, L.P, L.n, sh);
+    for (int k = tid; k < len; k += 256)
+        q[k + 1] = pass == 0 ? (double)((const TT *)L.tmpl)[base + k] : src[base + k];
+    if (tid == 0) q[0] = 0.0;
     __syncthreads();
-    box_pass(L.P, L.X, L.n, L.w);
-    for (int pass = 1; pass < 3; ++pass) {
-        __syncthreads();
-        prefix_pass((const double *)L.X, L.P, L.n, sh);
-        __syncthreads();
-        box_pass(L.P, L.X, L.n, L.w);
+    // inclusive scan of q[1 .. len]: runs of r consecutive values per thread
+    const int r = (len + 255) / 256;
+    const int a = 1 + tid * r, b = min(len + 1, a + r);
+    double run = 0.0;
+    for (int k = a; k < b; ++k) run += q[k];
+    tsum[tid] = run;
+    __syncthreads();
+    double off = 0.0;
+    for (int u = 0; u < tid; ++u) off += tsum[u];
+    for (int k = a; k < b; ++k) {
+        off += q[k];
+        q[k] = off;
+    }
+    __syncthreads();
+    for (int64_t i = t0 + tid; i < t1; i += 256) {
+        const int64_t lo = i - h > 0 ? i - h : 0, hi = i + h + 1 < n ? i + h + 1 : n;
+        dst[i] = (q[hi - base] - q[lo - base]) / (double)(hi - lo);
     }
 }
 
@@ -256,17 +234,24 @@ hipError_t launch_extract(const TraceDev *trs, int ntr, int nx, int ny, const vo
     return hipGetLastError();
 }
 
-hipError_t launch_smooth3(const void *lt_dev, int ntr, int f64, hipStream_t s)
+hipError_t launch_smooth3(const void *lt_dev, int ntr, int64_t nmax, int f64, hipStream_t s)
 {
-    if (ntr <= 0) return hipSuccess;
-    if (f64)
-        hipLaunchKernelGGL(k_smooth3<double>, dim3(ntr), dim3(256), 0, s,
-                           (const LoopTrace *)lt_dev);
-    else
-        hipLaunchKernelGGL(k_smooth3<float>, dim3(ntr), dim3(256), 0, s,
-                           (const LoopTrace *)lt_dev);
-    return hipGetLastError();
+    if (ntr <= 0 || nmax <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((nmax + SMT - 1) / SMT), ntr);
+    for (int pass = 0; pass < 3; ++pass) {
+        if (f64)
+            hipLaunchKernelGGL(k_box_pass<double>, grid, dim3(256), 0, s,
+                               (const LoopTrace *)lt_dev, pass);
+        else
+            hipLaunchKernelGGL(k_box_pass<float>, grid, dim3(256), 0, s,
+                               (const LoopTrace *)lt_dev, pass);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
+
+int loop_max_width() { return SMW; }
 
 hipError_t launch_ccf(const TraceDev *trs, int tr0, int ntr, const void *lt_dev, int nx,
                       const double *flux, const double *flat, const double *edges, double v0,

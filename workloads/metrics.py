@@ -34,3 +34,22 @@ def centroid(img: np.ndarray, i0: int = 0, j0: int = 0):
     tot = img.sum()
     jj, ii = np.indices(img.shape)
     return (float((img * (ii + i0)).sum() / tot), float((img * (jj + j0)).sum() / tot))
+
+
+def aliasing_level(frame: np.ndarray, scene, margin_px: int = 12) -> dict:
+    """Aliasing of a flat field rendered from discrete SFIs (Fig. 4): the
+    flux of a straight trace with a constant spectrum and uniform dispersion
+    is constant along x, so its relative RMS along the central row and along
+    the column sums, away from the trace ends, is the aliasing ripple.  The
+    photon-noise level is 1 / sqrt(mean count) of the same quantity."""
+    tr = scene.traces[0]
+    xs, xe = tr.cx[0] - tr.cx[1], tr.cx[0] + tr.cx[1]
+    cols = np.arange(int(np.ceil(xs)) + margin_px, int(np.floor(xe)) - margin_px)
+    yc = int(np.floor(tr.cy[0] + 0.5))
+    row = np.asarray(frame[yc, cols], np.float64)
+    col = np.asarray(frame[:, cols], np.float64).sum(0)
+    return {"row_ripple": float(np.std(row) / row.mean()),
+            "row_photon": float(1.0 / np.sqrt(row.mean())),
+            "col_ripple": float(np.std(col) / col.mean()),
+            "col_photon": float(1.0 / np.sqrt(col.mean())),
+            "row_mean": float(row.mean()), "columns": int(cols.size)}

@@ -422,3 +422,29 @@ def prnu_map(nx: int, ny: int, seed: int = 0, rms: float = 0.01) -> np.ndarray:
 XTALK_CCD = np.array([[0.0010, 0.0060, 0.0010],
                       [0.0040, 0.9760, 0.0040],
                       [0.0010, 0.0060, 0.0010]], dtype=np.float64)
+
+
+def aliasing_flat(per_res: float, subpix: int, *, seed: int = 3001, length_px: float = 1000.0,
+                  px_per_res: float = 4.5, rho: float = 2.0, sigma: float = 0.8,
+                  half_width: int = 5, ny: int = 32) -> Scene:
+    """Flat-field segment of one order, shaped after Fig. 4's ESPRESSO blue
+    arm (resolution element 0.02 A sampled by about 4.5 px, 10 SFIs per
+    element): a straight trace across `length_px` px, a constant spectrum of
+    `per_res` samples per resolution element, explicit SFIs (fiber disc of
+    radius rho px, Gaussian PSF sigma px) at `subpix` sub-pixels per pixel.
+    Photons per sample are set so that the trace's central row receives
+    about 4e4 e- per pixel."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx = int(length_px) + 4 * half_width + 8
+    n = int(round(length_px / px_per_res * per_res))
+    x0 = 2 * half_width + 4 + rng.uniform(0.0, 1.0)
+    lc, span = 450.0, 0.002 * length_px / px_per_res           # nm; 0.02 A per element
+    tr = Trace(order=146, fiber=0, slice=0, lmin=lc - span / 2, lmax=lc + span / 2, n=n,
+               cx=[x0 + length_px / 2, length_px / 2], cy=[ny / 2 + rng.uniform(-0.5, 0.5)],
+               thr=1.0, slot=0)
+    # central-row fraction of a disc (x) Gaussian image, about 0.2 for these sizes
+    phot = 4e4 / 0.21 * px_per_res / per_res
+    sxy = np.full((1, 1, 2), sigma, np.float32)
+    psf = Psf(kind="sfi", half_width=half_width, sigma_xy=sxy, fiber_radius=rho,
+              fiber_shape="disc", subpix=subpix)
+    return Scene("aliasing_flat", nx, ny, [tr], psf, [np.full(n, phot, np.float32)], "f64")
