@@ -10,7 +10,8 @@
 namespace e2e {
 hipError_t launch_extract(const TraceDev *trs, int ntr, int nx, int ny, const void *frame,
                           int f64, double A, double *flux, double *edges, hipStream_t s);
-hipError_t launch_smooth3(const void *lt_dev, int ntr, int64_t nmax, int f64, hipStream_t s);
+hipError_t launch_smooth3(const void *lt_dev, int ntr, int64_t nmax, int wmax, int f64,
+                          hipStream_t s);
 int loop_max_width();
 hipError_t launch_ccf(const TraceDev *trs, int tr0, int ntr, const void *lt_dev, int nx,
                       const double *flux, const double *flat, const double *edges, double v0,
@@ -201,8 +202,12 @@ extern "C" e2e_status e2e_ccf(e2e_ctx *ctx, e2e_format_id fmt, const e2e_ccf_req
             break;
         prof_begin(ctx, s, "template_smooth");
         int64_t ng = 0;
-        for (int q = 0; q < g; ++q) ng = std::max<int64_t>(ng, F->host[t0 + q].n);
-        e = launch_smooth3(ltd, g, ng, r->template_dtype == E2E_F64, s);
+        int wg = 1;
+        for (int q = 0; q < g; ++q) {
+            ng = std::max<int64_t>(ng, F->host[t0 + q].n);
+            wg = std::max(wg, w[t0 + q]);
+        }
+        e = launch_smooth3(ltd, g, ng, wg, r->template_dtype == E2E_F64, s);
         prof_end(ctx, s);
         if (e != hipSuccess) break;
         prof_begin(ctx, s, "ccf");

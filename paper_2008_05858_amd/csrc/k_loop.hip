@@ -8,11 +8,13 @@
 //    on x(t) (FP64), the edge wavelength, and the column's box extraction
 //    over the rows within +-A of the trace centre (fractional end rows).
 //    Neighbouring lanes read neighbouring pixels of each row.
-//  * k_box_pass (three launches): the three passes of a clipped moving
+//  * k_smooth3_fused / k_box_pass: the three passes of a clipped moving
 //    mean over the template (the input spectrum of the trace); one
 //    workgroup per 2048 outputs of a trace stages its inputs and the
-//    half-windows around them in LDS, scans them (FP64) and takes window
-//    differences, so every pass reads and writes each sample about once.
+//    windows around them in LDS, scans them (FP64) and takes window
+//    differences -- all three passes in one launch when the window is
+//    narrow (the template read once, the result written once), else one
+//    launch per pass.
 //  * k_ccf: one workgroup per (trace, 8 trial velocities): the mean of the
 //    flat-divided flux over the usable columns, then per column and
 //    velocity the template read at the Doppler-shifted column centre by
@@ -91,16 +93,44 @@ struct LoopTrace {
 constexpr int SMT = 2048;        // smoothed samples per workgroup
 constexpr int SMW = 4095;        // widest moving mean
 
+__device__ void lds_scan(double *q, int len, double *tsum)
+{
+    // q[1 .. len] -> inclusive prefix sums in place (q[0] = 0): each thread
+    // sums a run of consecutive values, the run totals are scanned with wave
+    // shuffles and the four wave totals (fixed order), then each thread
+    // rewrites its run
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int r = (len + 255) / 256;
+    const int a = 1 + tid * r, b = min(len + 1, a + r);
+    double run = 0.0;
+    for (int k = a; k < b; ++k) run += q[k];
+    double x = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) tsum[wv] = x;
+    __syncthreads();
+    double off = x - run;
+    for (int u = 0; u < wv; ++u) off += tsum[u];
+    for (int k = a; k < b; ++k) {
+        off += q[k];
+        q[k] = off;
+    }
+    __syncthreads();
+}
+
 // One moving-mean pass over a tile of SMT outputs of one trace: the tile's
-// inputs with a half-window on each side are staged in LDS, scanned (FP64,
-// 256 threads x consecutive runs), and each output is the window sum (the
+// inputs with a half-window on each side are staged in LDS, scanned (FP64),
+// and each output is the window sum (the
 // window clipped to the array) over its count.  Pass 0 reads the template
 // into X, pass 1 X into P, pass 2 P into X.
 template <typename TT>
 __global__ __launch_bounds__(256) void k_box_pass(const LoopTrace *__restrict__ lt, int pass)
 {
     __shared__ double q[SMT + SMW + 1];
-    __shared__ double tsum[256];
+    __shared__ double tsum[4];
     const LoopTrace L = lt[blockIdx.y];
     const int64_t n = L.n, h = L.w / 2;
     const int64_t t0 = (int64_t)blockIdx.x * SMT;
@@ -115,23 +145,56 @@ __global__ __launch_bounds__(256) void k_box_pass(const LoopTrace *__restrict__ 
         q[k + 1] = pass == 0 ? (double)((const TT *)L.tmpl)[base + k] : src[base + k];
     if (tid == 0) q[0] = 0.0;
     __syncthreads();
-    // inclusive scan of q[1 .. len]: runs of r consecutive values per thread
-    const int r = (len + 255) / 256;
-    const int a = 1 + tid * r, b = min(len + 1, a + r);
-    double run = 0.0;
-    for (int k = a; k < b; ++k) run += q[k];
-    tsum[tid] = run;
-    __syncthreads();
-    double off = 0.0;
-    for (int u = 0; u < tid; ++u) off += tsum[u];
-    for (int k = a; k < b; ++k) {
-        off += q[k];
-        q[k] = off;
-    }
-    __syncthreads();
+    lds_scan(q, len, tsum);
     for (int64_t i = t0 + tid; i < t1; i += 256) {
         const int64_t lo = i - h > 0 ? i - h : 0, hi = i + h + 1 < n ? i + h + 1 : n;
         dst[i] = (q[hi - base] - q[lo - base]) / (double)(hi - lo);
+    }
+}
+
+// All three passes in one launch when the windows are narrow (6h <= SMT):
+// a workgroup loads its SMT outputs with 3h on each side, and pass k
+// (k = 1, 2, 3) produces the range widened by (3 - k) h from the previous
+// one in LDS (scan, window differences).  The template is read once and the
+// smoothed template written once; the halo is recomputed by the neighbours.
+constexpr int SFH = SMT / 6;     // widest half-window of the fused form
+
+template <typename TT>
+__global__ __launch_bounds__(256) void k_smooth3_fused(const LoopTrace *__restrict__ lt)
+{
+    __shared__ double qa[SMT + 6 * SFH + 2], qb[SMT + 6 * SFH + 2];
+    __shared__ double tsum[4];
+    const LoopTrace L = lt[blockIdx.y];
+    const int64_t n = L.n, h = L.w / 2;
+    const int64_t t0 = (int64_t)blockIdx.x * SMT;
+    if (t0 >= n) return;
+    const int64_t t1 = t0 + SMT < n ? t0 + SMT : n;
+    const int tid = threadIdx.x;
+    int64_t b = t0 - 3 * h > 0 ? t0 - 3 * h : 0, e = t1 + 3 * h < n ? t1 + 3 * h : n;
+    int len = (int)(e - b);
+    for (int k = tid; k < len; k += 256) qa[k + 1] = (double)((const TT *)L.tmpl)[b + k];
+    if (tid == 0) qa[0] = 0.0;
+    __syncthreads();
+    double *src = qa, *dst = qb;
+    for (int pass = 1; pass <= 3; ++pass) {
+        lds_scan(src, len, tsum);
+        const int64_t wb = (int64_t)(3 - pass) * h;
+        const int64_t nb = t0 - wb > 0 ? t0 - wb : 0, ne = t1 + wb < n ? t1 + wb : n;
+        const int nlen = (int)(ne - nb);
+        for (int k = tid; k < nlen; k += 256) {
+            const int64_t i = nb + k;
+            const int64_t lo = i - h > 0 ? i - h : 0, hi = i + h + 1 < n ? i + h + 1 : n;
+            const double v = (src[hi - b] - src[lo - b]) / (double)(hi - lo);
+            if (pass < 3) dst[k + 1] = v;
+            else L.X[i] = v;
+        }
+        if (tid == 0) dst[0] = 0.0;
+        __syncthreads();
+        double *t = src;
+        src = dst;
+        dst = t;
+        b = nb;
+        len = nlen;
     }
 }
 
@@ -234,10 +297,20 @@ hipError_t launch_extract(const TraceDev *trs, int ntr, int nx, int ny, const vo
     return hipGetLastError();
 }
 
-hipError_t launch_smooth3(const void *lt_dev, int ntr, int64_t nmax, int f64, hipStream_t s)
+hipError_t launch_smooth3(const void *lt_dev, int ntr, int64_t nmax, int wmax, int f64,
+                          hipStream_t s)
 {
     if (ntr <= 0 || nmax <= 0) return hipSuccess;
     const dim3 grid((unsigned)((nmax + SMT - 1) / SMT), ntr);
+    if (wmax / 2 <= SFH) {
+        if (f64)
+            hipLaunchKernelGGL(k_smooth3_fused<double>, grid, dim3(256), 0, s,
+                               (const LoopTrace *)lt_dev);
+        else
+            hipLaunchKernelGGL(k_smooth3_fused<float>, grid, dim3(256), 0, s,
+                               (const LoopTrace *)lt_dev);
+        return hipGetLastError();
+    }
     for (int pass = 0; pass < 3; ++pass) {
         if (f64)
             hipLaunchKernelGGL(k_box_pass<double>, grid, dim3(256), 0, s,
