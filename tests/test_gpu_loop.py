@@ -169,3 +169,25 @@ def test_c1_full_size():
     print(f"[c1 round trip] rv {rv:.3f} m/s (injected {v0})", flush=True)
     assert abs(rv - v0) < 20.0
     ld.free()
+
+
+def test_extract_aperture_over_the_edge():
+    """Traces whose aperture reaches past the first / last detector row and
+    whose x range runs past the side edges: only on-chip rows and columns
+    are extracted, as in the oracle."""
+    from paper_2008_05858_amd import Loaded
+    from workloads import Psf, Scene, Trace
+    print("case extraction near the detector edges", flush=True)
+    trs = [Trace(0, 0, 0, 500.0, 505.0, 3000, [40.0, 50.0, 2.0], [1.2, 0.8], 1.0, 0),
+           Trace(1, 0, 0, 505.0, 510.0, 3000, [50.0, 45.0], [62.5, -0.6, 0.3], 1.0, 0)]
+    sc = Scene("edges", 96, 64, trs, Psf(kind="erf", sigma=1.1, half_width=4),
+               [np.full(3000, 1e3)], "f64")
+    F = oracle.render(sc)
+    ld = Loaded(_gu().ctx(), sc)
+    Eg, Lg = gpu_extract(ld, sc, F, 4.5)
+    Eo, Lo = oracle.extract(sc, F, 4.5)
+    assert np.array_equal(np.isnan(Lg), np.isnan(Lo))
+    ok = ~np.isnan(Lo)
+    assert np.max(np.abs(Lg[ok] - Lo[ok])) < 1e-10
+    assert np.max(np.abs(Eg - Eo)) <= 1e-12 * np.abs(Eo).max()
+    ld.free()

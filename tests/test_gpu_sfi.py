@@ -108,3 +108,22 @@ def test_c5_sfi_full_frame_sampled():
           flush=True)
     assert err < TOL
     del torch
+
+
+def test_sfi_trace_off_detector_edges():
+    """A trace whose windows hang over the bottom and both side edges: flux
+    falling off the chip is dropped on both sides (nothing renormalised)."""
+    import dataclasses
+    print("case mini_sfi trace over the detector edges", flush=True)
+    sc = scene("mini_sfi", n_samp=300)
+    t = sc.traces[0]
+    # x from -6 to 126 px.  Generic coefficients: with round ones (60 + 66 t)
+    # some samples sit exactly on a half-integer x, where the window anchor
+    # floor(x + 1/2) depends on the last bit of x and the renormalised
+    # window legitimately jumps by the truncated tail (~1e-5 of the peak).
+    t2 = dataclasses.replace(t, cx=[60.0123, 66.0371], cy=[1.3117, 0.4029])
+    sc = dataclasses.replace(sc, traces=[t2])
+    g = _gu().render(sc)
+    o = oracle.render(sc)
+    assert _report("mini_sfi-edges", g, o) < TOL
+    assert o.sum() < 0.9 * float(np.sum(sc.spectra[0]))
