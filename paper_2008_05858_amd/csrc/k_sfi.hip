@@ -37,6 +37,7 @@ namespace e2e {
 namespace {
 
 constexpr int CH = 16;                   // samples per chunk
+constexpr int PB = 64;                   // samples positioned together
 constexpr int NW = 2 * kSfiMaxH + 1;     // window edge, max
 
 // Normal tail Phi(-|z|) = erfc(|z| / sqrt 2) / 2, branch free: the
@@ -91,9 +92,10 @@ __global__ __launch_bounds__(256) void k_render_sfi(const FrameDev *__restrict__
     constexpr int TW = kSfiTW, TH = kSfiTH;
     __shared__ float sX[CH][kSfiMaxR][NW + 1], sY[CH][kSfiMaxR][NW + 1];
     __shared__ float sSX[CH][kSfiMaxR];
-    __shared__ float sdx[CH], sdy[CH], ssx[CH], ssy[CH], sphi[CH];
-    __shared__ double sscale[CH];
-    __shared__ int sax[CH], say[CH];
+    __shared__ double sprod[CH][kSfiMaxR];
+    __shared__ float sdx[PB], sdy[PB], ssx[PB], ssy[PB], sphi[PB];
+    __shared__ double sscale[PB];
+    __shared__ int sax[PB], say[PB];
     __shared__ int tlist[kMaxTileTraces];
     __shared__ int sh_count, sh_item;
 
@@ -162,11 +164,11 @@ __global__ __launch_bounds__(256) void k_render_sfi(const FrameDev *__restrict__
             trace_affine(T, F.beta, &t0, &dt);
             const float scale = (float)(T.thr * F.flux_scale);
             const ST *spec = (const ST *)F.spec[T.slot];
-            for (int kc = sg.k0; kc < sg.k1; kc += CH) {
-                const int nk = min(CH, sg.k1 - kc);
-                // 1. positions, anchors, sigmas, photons
-                if (tid < nk) {
-                    const int k = kc + tid;
+            for (int kb = sg.k0; kb < sg.k1; kb += PB) {
+                const int nb = min(PB, sg.k1 - kb);
+                // 1. positions, anchors, sigmas, photons of up to 64 samples
+                if (tid < nb) {
+                    const int k = kb + tid;
                     const double t = fma((double)k, dt, t0);
                     const double x = horner<DX>(cxr, t);
                     const double y = horner<DY>(cyr, t);
@@ -182,80 +184,90 @@ __global__ __launch_bounds__(256) void k_render_sfi(const FrameDev *__restrict__
                     say[tid] = (int)ayd - H;
                 }
                 __syncthreads();
-                // 2. X_p rows (one (sample, point) per task) and Y_p entries
-                //    (one (sample, point, pixel row) per task: the normal tails
-                //    are the costly part, so they are spread finest)
-                const int nX = nk * R, nT = nX + nk * R * N;
-                for (int q = tid; q < nT; q += 256) {
-                    if (q < nX) {
-                        const int s = q / R, p = q % R;
-                        const float a = F.sfq[3 * p], wp = F.sfq[3 * p + 2];
-                        const float inv = 1.0f / ssx[s], d = sdx[s];
-                        float tot = 0.0f;
-                        for (int i = 0; i < N; ++i) {
-                            float g = 0.0f;
-                            for (int t = 0; t < S; ++t) {
-                                const float u = (float)(i - H) - 0.5f + ((float)t + 0.5f) * invS - d;
-                                g += gauss((u - a) * inv) + gauss((u + a) * inv);
+                for (int c0 = 0; c0 < nb; c0 += CH) {
+                    const int nk = min(CH, nb - c0);
+                    // 2. X_p rows (one (sample, point) per task) and Y_p
+                    //    entries (one (sample, point, pixel row) per task: the
+                    //    normal tails are the costly part, so they are spread
+                    //    finest); s indexes the chunk, c0 + s the block
+                    const int nX = nk * R, nT = nX + nk * R * N;
+                    for (int q = tid; q < nT; q += 256) {
+                        if (q < nX) {
+                            const int s = q / R, p = q % R;
+                            const float a = F.sfq[3 * p], wp = F.sfq[3 * p + 2];
+                            const float inv = 1.0f / ssx[c0 + s], d = sdx[c0 + s];
+                            float tot = 0.0f;
+                            for (int i = 0; i < N; ++i) {
+                                float g = 0.0f;
+                                for (int t = 0; t < S; ++t) {
+                                    const float u =
+                                        (float)(i - H) - 0.5f + ((float)t + 0.5f) * invS - d;
+                                    g += gauss((u - a) * inv) + gauss((u + a) * inv);
+                                }
+                                g *= wp;
+                                sX[s][p][i] = g;
+                                tot += g;
                             }
-                            g *= wp;
-                            sX[s][p][i] = g;
-                            tot += g;
+                            sSX[s][p] = tot;
+                        } else {
+                            const int e = q - nX, s = e / (R * N), rem = e % (R * N);
+                            const int p = rem / N, j = rem % N;
+                            const float h = F.sfq[3 * p + 1];
+                            const float inv = 1.0f / ssy[c0 + s];
+                            const float lo = shape == E2E_FIBER_HALF_UP ? 0.0f : -h;
+                            const float hi = shape == E2E_FIBER_HALF_DOWN ? 0.0f : h;
+                            const float v0 = (float)(j - H) - 0.5f - sdy[c0 + s];
+                            float g0 = 0.0f, g1 = 0.0f;
+                            int t = 0;
+                            for (; t + 1 < S; t += 2) {   // two sub-rows: four independent tails
+                                const float va = v0 + ((float)t + 0.5f) * invS;
+                                const float vb = v0 + ((float)t + 1.5f) * invS;
+                                g0 += cdf_diff((va - lo) * inv, (va - hi) * inv);
+                                g1 += cdf_diff((vb - lo) * inv, (vb - hi) * inv);
+                            }
+                            if (t < S) {
+                                const float va = v0 + ((float)t + 0.5f) * invS;
+                                g0 += cdf_diff((va - lo) * inv, (va - hi) * inv);
+                            }
+                            sY[s][p][j] = g0 + g1;
                         }
-                        sSX[s][p] = tot;
-                    } else {
-                        const int e = q - nX, s = e / (R * N), rem = e % (R * N);
-                        const int p = rem / N, j = rem % N;
-                        const float h = F.sfq[3 * p + 1];
-                        const float inv = 1.0f / ssy[s];
-                        const float lo = shape == E2E_FIBER_HALF_UP ? 0.0f : -h;
-                        const float hi = shape == E2E_FIBER_HALF_DOWN ? 0.0f : h;
-                        const float v0 = (float)(j - H) - 0.5f - sdy[s];
-                        float g0 = 0.0f, g1 = 0.0f;
-                        int t = 0;
-                        for (; t + 1 < S; t += 2) {   // two sub-rows: four independent tails
-                            const float va = v0 + ((float)t + 0.5f) * invS;
-                            const float vb = v0 + ((float)t + 1.5f) * invS;
-                            g0 += cdf_diff((va - lo) * inv, (va - hi) * inv);
-                            g1 += cdf_diff((vb - lo) * inv, (vb - hi) * inv);
-                        }
-                        if (t < S) {
-                            const float va = v0 + ((float)t + 0.5f) * invS;
-                            g0 += cdf_diff((va - lo) * inv, (va - hi) * inv);
-                        }
-                        sY[s][p][j] = g0 + g1;
                     }
-                }
-                __syncthreads();
-                // 3. scale of each sample: photons over its window sum
-                if (tid < nk) {
-                    double z = 0.0;
-                    for (int p = 0; p < R; ++p) {
+                    __syncthreads();
+                    // 3. scale of each sample: photons over its window sum
+                    //    sum_p (sum_i X_p[i]) (sum_j Y_p[j]), one (sample, point)
+                    //    per thread, then the sums over the points in order
+                    if (tid < nX) {
+                        const int s = tid / R, p = tid % R;
                         float sy = 0.0f;
-                        for (int j = 0; j < N; ++j) sy += sY[tid][p][j];
-                        z += (double)sSX[tid][p] * (double)sy;
+                        for (int j = 0; j < N; ++j) sy += sY[s][p][j];
+                        sprod[s][p] = (double)sSX[s][p] * (double)sy;
                     }
-                    sscale[tid] = (double)sphi[tid] / z;
-                }
-                __syncthreads();
-                // 4. this thread's pixels, samples in order
-                for (int s = 0; s < nk; ++s) {
-                    const int di = pi - sax[s], dj0 = pj - say[s];
-                    if ((unsigned)di < (unsigned)N && dj0 > -8 && dj0 < N) {
-                        const double sc = sscale[s];
+                    __syncthreads();
+                    if (tid < nk) {
+                        double z = 0.0;
+                        for (int p = 0; p < R; ++p) z += sprod[tid][p];
+                        sscale[c0 + tid] = (double)sphi[c0 + tid] / z;
+                    }
+                    __syncthreads();
+                    // 4. this thread's pixels, samples in order
+                    for (int s = 0; s < nk; ++s) {
+                        const int di = pi - sax[c0 + s], dj0 = pj - say[c0 + s];
+                        if ((unsigned)di < (unsigned)N && dj0 > -8 && dj0 < N) {
+                            const double sc = sscale[c0 + s];
 #pragma unroll
-                        for (int r = 0; r < 8; ++r) {
-                            const int dj = dj0 + r;
-                            if ((unsigned)dj < (unsigned)N) {
-                                float v = 0.0f;
-                                for (int p = 0; p < R; ++p)
-                                    v = fmaf(sX[s][p][di], sY[s][p][dj], v);
-                                acc[r] = fma((double)v, sc, acc[r]);
+                            for (int r = 0; r < 8; ++r) {
+                                const int dj = dj0 + r;
+                                if ((unsigned)dj < (unsigned)N) {
+                                    float v = 0.0f;
+                                    for (int p = 0; p < R; ++p)
+                                        v = fmaf(sX[s][p][di], sY[s][p][dj], v);
+                                    acc[r] = fma((double)v, sc, acc[r]);
+                                }
                             }
                         }
                     }
+                    __syncthreads();
                 }
-                __syncthreads();
             }
         }
 #pragma unroll
