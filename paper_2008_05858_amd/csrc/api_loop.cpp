@@ -40,6 +40,27 @@ struct Bufs {
     }
 };
 
+// Holds a reference on a format for the duration of a call, so that
+// e2e_format_free reports E2E_EBUSY instead of freeing it underneath.
+struct FormatRef {
+    e2e_ctx *ctx;
+    FormatRes *F = nullptr;
+    FormatRef(e2e_ctx *c, e2e_format_id id) : ctx(c)
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->fmts.find(id);
+        if (it == ctx->fmts.end()) return;
+        F = it->second;
+        F->refs++;
+    }
+    ~FormatRef()
+    {
+        if (!F) return;
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        F->refs--;
+    }
+};
+
 double horner_host(const double *c, int deg, double t)
 {
     double v = c[deg];
@@ -56,14 +77,9 @@ extern "C" e2e_status e2e_extract(e2e_ctx *ctx, e2e_format_id fmt, const void *f
     if (!ctx || !frame || !flux || !edges) return fail(E2E_EINVAL, "e2e_extract: NULL argument");
     if (dtype != E2E_F32 && dtype != E2E_F64) return fail(E2E_EINVAL, "dtype=%d", dtype);
     if (!(std::isfinite(A) && A > 0.0)) return fail(E2E_EINVAL, "aperture_half_px=%g", A);
-    FormatRes *F;
-    {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        auto it = ctx->fmts.find(fmt);
-        if (it == ctx->fmts.end())
-            return fail(E2E_ENOTFOUND, "format %llu not found", (unsigned long long)fmt);
-        F = it->second;
-    }
+    FormatRef ref(ctx, fmt);
+    FormatRes *F = ref.F;
+    if (!F) return fail(E2E_ENOTFOUND, "format %llu not found", (unsigned long long)fmt);
     hipSetDevice(ctx->dev);
     hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
     const size_t npx = (size_t)F->nx * F->ny, fb = npx * (dtype == E2E_F64 ? 8 : 4);
@@ -109,14 +125,9 @@ extern "C" e2e_status e2e_ccf(e2e_ctx *ctx, e2e_format_id fmt, const e2e_ccf_req
     if (vmax > 1.5e7) return fail(E2E_EINVAL, "e2e_ccf: |v| above 1.5e7 m/s");
     if (!(std::isfinite(r->smooth_px) && r->smooth_px > 0.0))
         return fail(E2E_EINVAL, "smooth_px=%g", r->smooth_px);
-    FormatRes *F;
-    {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        auto it = ctx->fmts.find(fmt);
-        if (it == ctx->fmts.end())
-            return fail(E2E_ENOTFOUND, "format %llu not found", (unsigned long long)fmt);
-        F = it->second;
-    }
+    FormatRef ref(ctx, fmt);
+    FormatRes *F = ref.F;
+    if (!F) return fail(E2E_ENOTFOUND, "format %llu not found", (unsigned long long)fmt);
     if (r->n_templates < F->nslots)
         return fail(E2E_EINVAL, "n_templates=%d, the format uses %d", r->n_templates, F->nslots);
     hipSetDevice(ctx->dev);
