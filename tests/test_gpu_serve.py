@@ -44,12 +44,13 @@ def test_serve_mix_equals_alone():
     from paper_2008_05858_amd import e2e as E
     gu = _gu()
     ctx = E.e2e_create(0, 0)
-    scs = {"t": scene("mini_table"), "c0": scene("c0"), "h": scene("mini_hires")}
+    scs = {"t": scene("mini_table"), "c0": scene("c0"), "h": scene("mini_hires"),
+           "s": scene("mini_sfi")}
     lds = {k: P.Loaded(ctx, v) for k, v in scs.items()}
     dev = {k: gu.device_spectra(v) for k, v in scs.items()}
     rng = np.random.default_rng(5)
-    plan = [(["t", "c0", "h"][i % 3], float(rng.uniform(-10, 10)), float(rng.uniform(0.5, 2)))
-            for i in range(18)]
+    plan = [(["t", "c0", "h", "s"][i % 4], float(rng.uniform(-10, 10)),
+             float(rng.uniform(0.5, 2))) for i in range(20)]
     # references: alone, plain renderer
     refs = []
     for name, rv, fs in plan:
@@ -71,7 +72,7 @@ def test_serve_mix_equals_alone():
         tickets[idx] = E.e2e_serve_submit(ctx, r)
 
     torch.cuda.synchronize()
-    print("case serve: 18 requests from 3 threads", flush=True)
+    print("case serve: 20 requests (table, erf, HIRES tables, explicit SFI) from 3 threads", flush=True)
     ths = [threading.Thread(target=lambda s=s: [submit(i) for i in range(s, len(plan), 3)])
            for s in range(3)]
     for t in ths:
