@@ -328,7 +328,8 @@ def secondary(E, P, torch, ctx, sc1, ld1, specs1, log):
                      "subpixel_evals_per_s": n_sfi * w * w * c5.psf.subpix ** 2 / (ms / 1e3),
                      "window_px": w, "subpixels": c5.psf.subpix,
                      "fiber_radius_px": c5.psf.fiber_radius,
-                     "paper_s_per_sfi_k80": 0.17}
+                     "paper_s_per_sfi_k80": 0.17,
+                     "sfi_rate_vs_paper_k80": n_sfi / (ms / 1e3) * 0.17}
     ld5.free()
     return res
 
