@@ -332,7 +332,7 @@ e2e_status e2e_detector(e2e_ctx *ctx, const e2e_detector_desc *d, const void *fr
  * flux is [ntr][nx] FP64, edges [ntr][nx+1] FP64.  on_device = 1: all
  * three arrays are device pointers and the work is ordered on hip_stream
  * (NULL: the context's stream); 0: host arrays, staged.  Returns when done.
- * Errors: E2E_EINVAL (NULL pointers, bad dtype, A <= 0 or not finite),
+ * Errors: E2E_EINVAL (NULL pointers, bad dtype, A outside (0, 1e6]),
  * E2E_ENOTFOUND (fmt), E2E_ENOMEM, E2E_EDEVICE.
  */
 e2e_status e2e_extract(e2e_ctx *ctx, e2e_format_id fmt, const void *frame, int32_t frame_dtype,

@@ -76,7 +76,8 @@ extern "C" e2e_status e2e_extract(e2e_ctx *ctx, e2e_format_id fmt, const void *f
 {
     if (!ctx || !frame || !flux || !edges) return fail(E2E_EINVAL, "e2e_extract: NULL argument");
     if (dtype != E2E_F32 && dtype != E2E_F64) return fail(E2E_EINVAL, "dtype=%d", dtype);
-    if (!(std::isfinite(A) && A > 0.0)) return fail(E2E_EINVAL, "aperture_half_px=%g", A);
+    if (!(std::isfinite(A) && A > 0.0 && A <= 1e6))
+        return fail(E2E_EINVAL, "aperture_half_px=%g", A);
     FormatRef ref(ctx, fmt);
     FormatRes *F = ref.F;
     if (!F) return fail(E2E_ENOTFOUND, "format %llu not found", (unsigned long long)fmt);
