@@ -45,7 +45,11 @@ def test_null_arguments_are_rejected_without_device():
     assert L.e2e_render_batch(None, None, 1) == E.E2E_EINVAL
     assert L.e2e_serve_poll(None, 1, 0, None) == E.E2E_EINVAL
     assert L.e2e_noise_poisson(None, None, 0, 1, 0, 0, 0, None) == E.E2E_EINVAL
-    assert "NULL" in E.e2e_last_error()
+    assert L.e2e_detector(None, None, None, 0, None, 1, 1, None, 0, None) == E.E2E_EINVAL
+    assert L.e2e_extract(None, 1, None, 0, 1.0, None, None, 0, None) == E.E2E_EINVAL
+    assert L.e2e_ccf(None, 1, None, None) == E.E2E_EINVAL
+    assert L.e2e_autotune(None, None, 1, None) == E.E2E_EINVAL
+    assert "NULL" in E.e2e_last_error() or "bad arguments" in E.e2e_last_error()
     L.e2e_destroy(None)
 
 
