@@ -8,9 +8,10 @@
 // Positions are FP64; the CDF differences are evaluated in FP32 on
 // pixel-relative offsets (|offset| <= H + 1), each edge through one erfc on
 // the side of the distribution where nothing cancels.  One workgroup owns a
-// 16 x 16 tile, stages 256 samples' per-axis weights in LDS and lets each
-// thread gather its pixel's contributions in sample order (FP64 or FP32
-// sums), so the result is deterministic and written once.
+// 16 x 16 tile, stages 256 samples' per-axis weights in LDS, aligned to the
+// tile's columns and rows (zero outside each window), and lets each thread
+// add its pixel's products in sample order (FP64 or FP32 sums), so the
+// result is deterministic and written once.
 #include "psf_gauss.h"
 
 namespace e2e {
@@ -26,9 +27,10 @@ __global__ __launch_bounds__(256) void k_render_sep(const FrameDev *__restrict__
                                                     int *__restrict__ err)
 {
     constexpr int TS = kSepTile;
-    constexpr int WMAX = 2 * kMaxH + 1;
-    __shared__ int sax[kChunk], say[kChunk];
-    __shared__ float swx[kChunk][WMAX + 1], swy[kChunk][WMAX + 1];
+    static_assert(TS == 16, "tile-aligned weights are 16 wide");
+    // per staged sample, its weights on the tile's 16 columns / 16 rows
+    // (zero outside its window)
+    __shared__ float swx[kChunk][TS], swy[kChunk][TS];
     __shared__ int tlist[kMaxTileTraces];
     __shared__ int sh_count, sh_item;
 
@@ -107,20 +109,20 @@ __global__ __launch_bounds__(256) void k_render_sep(const FrameDev *__restrict__
                         sgx = sgy = (float)F.sigma;
                     }
                     float phi = (float)spec_at(spec, k) * scale;
-                    axis_weights((float)(x - axd), sgx, H, phi, swx[tid]);
-                    axis_weights((float)(y - ayd), sgy, H, 1.0f, swy[tid]);
-                    sax[tid] = (int)axd - H;
-                    say[tid] = (int)ayd - H;
+                    axis_weights_tile((float)(x - axd), sgx, H, phi, (int)axd - H - X0,
+                                      swx[tid]);
+                    axis_weights_tile((float)(y - ayd), sgy, H, 1.0f, (int)ayd - H - Y0,
+                                      swy[tid]);
                 }
                 __syncthreads();
-                const int W = 2 * H;
+                // every staged sample in order; outside its window both
+                // weights' product is 0 and leaves the sum unchanged
+                const int tcx = tid % TS, tcy = tid / TS;
+#pragma unroll 4
                 for (int s = 0; s < nk; ++s) {
-                    int dx = pi - sax[s], dy = pj - say[s];
-                    if ((unsigned)dx <= (unsigned)W && (unsigned)dy <= (unsigned)W) {
-                        float v = swx[s][dx] * swy[s][dy];
-                        if (ACC64) acc64 += (double)v;
-                        else acc32 += v;
-                    }
+                    const float v = swx[s][tcx] * swy[s][tcy];
+                    if (ACC64) acc64 += (double)v;
+                    else acc32 += v;
                 }
                 __syncthreads();
             }

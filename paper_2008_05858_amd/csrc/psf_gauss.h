@@ -42,6 +42,43 @@ __device__ inline void axis_weights(float d, float sg, int H, float scale, float
 }
 
 
+// The same weights, written aligned to a 16-pixel tile: window pixel m
+// (0 .. 2H) lands in w16[off + m] when that is inside the tile, every other
+// entry is 0.  The window sum is taken from the two outer edges first, so
+// each weight is stored once, already scaled; the values are bit-identical
+// to axis_weights().
+__device__ inline void axis_weights_tile(float d, float sg, int H, float scale, int off,
+                                         float *w16)
+{
+    const float r = 0.70710678118654752f;
+    float inv = 1.0f / sg;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) w16[c] = 0.0f;
+    const float c0 = 0.5f * erfcf(fabsf(((float)(0 - H) - 0.5f - d) * inv) * r);
+    const float clast = 0.5f * erfcf(fabsf(((float)(2 * H + 1 - H) - 0.5f - d) * inv) * r);
+    const float f = scale / ((1.0f - c0) - clast);
+    float cprev = c0;
+    bool pprev = false;  // the first edge lies left of the centre
+    const int m0 = max(1, 1 - off), m1 = min(2 * H + 1, 16 - off);
+    if (m0 > 1) {
+        const float e = ((float)(m0 - 1 - H) - 0.5f - d) * inv;
+        cprev = 0.5f * erfcf(fabsf(e) * r);
+        pprev = e >= 0.0f;
+    }
+    for (int m = m0; m <= m1; ++m) {
+        const float e = ((float)(m - H) - 0.5f - d) * inv;
+        const float c = m == 2 * H + 1 ? clast : 0.5f * erfcf(fabsf(e) * r);
+        const bool pos = e >= 0.0f;
+        float v;
+        if (pprev) v = cprev - c;
+        else if (!pos) v = c - cprev;
+        else v = (1.0f - cprev) - c;
+        w16[off + m - 1] = v * f;
+        cprev = c;
+        pprev = pos;
+    }
+}
+
 // (sigma_x, sigma_y) of a sample: bilinear in the field over the node grid.
 __device__ inline void sigma_at(const float *sxy, int gx, int gy, double gsx, double gsy,
                                 double x, double y, float *sx, float *sy)
