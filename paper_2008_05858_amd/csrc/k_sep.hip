@@ -30,7 +30,8 @@ __global__ __launch_bounds__(256) void k_render_sep(const FrameDev *__restrict__
     static_assert(TS == 16, "tile-aligned weights are 16 wide");
     // per staged sample, its weights on the tile's 16 columns / 16 rows
     // (zero outside its window)
-    __shared__ float swx[kChunk][TS], swy[kChunk][TS];
+    __shared__ __align__(16) float swx[kChunk][TS];
+    __shared__ __align__(16) float swy[kChunk][TS];
     __shared__ int tlist[kMaxTileTraces];
     __shared__ int sh_count, sh_item;
 

@@ -42,24 +42,25 @@ __device__ inline void axis_weights(float d, float sg, int H, float scale, float
 }
 
 
-// The same weights, written aligned to a 16-pixel tile: window pixel m
-// (0 .. 2H) lands in w16[off + m] when that is inside the tile, every other
-// entry is 0.  The window sum is taken from the two outer edges first, so
-// each weight is stored once, already scaled; the values are bit-identical
-// to axis_weights().
+// The same weights, written aligned to a tile edge of TWD pixels: window
+// pixel m (0 .. 2H) lands in w16[off + m] when that is inside the tile,
+// every other entry is 0.  The window sum is taken
+// from the two outer edges first, so each weight is stored once, already
+// scaled; the values are bit-identical to axis_weights().
+template <int TWD = 16>
 __device__ inline void axis_weights_tile(float d, float sg, int H, float scale, int off,
                                          float *w16)
 {
     const float r = 0.70710678118654752f;
     float inv = 1.0f / sg;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) w16[c] = 0.0f;
+    for (int c = 0; c < TWD; ++c) w16[c] = 0.0f;
     const float c0 = 0.5f * erfcf(fabsf(((float)(0 - H) - 0.5f - d) * inv) * r);
     const float clast = 0.5f * erfcf(fabsf(((float)(2 * H + 1 - H) - 0.5f - d) * inv) * r);
     const float f = scale / ((1.0f - c0) - clast);
     float cprev = c0;
     bool pprev = false;  // the first edge lies left of the centre
-    const int m0 = max(1, 1 - off), m1 = min(2 * H + 1, 16 - off);
+    const int m0 = max(1, 1 - off), m1 = min(2 * H + 1, TWD - off);
     if (m0 > 1) {
         const float e = ((float)(m0 - 1 - H) - 0.5f - d) * inv;
         cprev = 0.5f * erfcf(fabsf(e) * r);
