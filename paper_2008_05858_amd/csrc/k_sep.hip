@@ -29,9 +29,13 @@ __global__ __launch_bounds__(256) void k_render_sep(const FrameDev *__restrict__
     constexpr int TS = kSepTile;
     static_assert(TS == 16, "tile-aligned weights are 16 wide");
     // per staged sample, its weights on the tile's 16 columns / 16 rows
-    // (zero outside its window)
-    __shared__ __align__(16) float swx[kChunk][TS];
-    __shared__ __align__(16) float swy[kChunk][TS];
+    // (zero outside its window), stored column-major ([pixel][sample]) so a
+    // thread reads four consecutive samples' weights in one 16-byte load
+    // (rows padded by 4 floats: the 16 rows read together start on
+    // different banks)
+    constexpr int RS = kChunk + 4;
+    __shared__ __align__(16) float swx[TS][RS];
+    __shared__ __align__(16) float swy[TS][RS];
     __shared__ int tlist[kMaxTileTraces];
     __shared__ int sh_count, sh_item;
 
@@ -110,20 +114,38 @@ __global__ __launch_bounds__(256) void k_render_sep(const FrameDev *__restrict__
                         sgx = sgy = (float)F.sigma;
                     }
                     float phi = (float)spec_at(spec, k) * scale;
-                    axis_weights_tile((float)(x - axd), sgx, H, phi, (int)axd - H - X0,
-                                      swx[tid]);
-                    axis_weights_tile((float)(y - ayd), sgy, H, 1.0f, (int)ayd - H - Y0,
-                                      swy[tid]);
+                    axis_weights_tile<TS, RS>((float)(x - axd), sgx, H, phi,
+                                              (int)axd - H - X0, &swx[0][tid]);
+                    axis_weights_tile<TS, RS>((float)(y - ayd), sgy, H, 1.0f,
+                                              (int)ayd - H - Y0, &swy[0][tid]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < TS; ++c) {
+                        swx[c][tid] = 0.0f;
+                        swy[c][tid] = 0.0f;
+                    }
                 }
                 __syncthreads();
-                // every staged sample in order; outside its window both
-                // weights' product is 0 and leaves the sum unchanged
+                // every staged sample in order (four per 16-byte read); outside
+                // its window both weights' product is 0 and leaves the sum
+                // unchanged
                 const int tcx = tid % TS, tcy = tid / TS;
-#pragma unroll 4
-                for (int s = 0; s < nk; ++s) {
-                    const float v = swx[s][tcx] * swy[s][tcy];
-                    if (ACC64) acc64 += (double)v;
-                    else acc32 += v;
+                const float4 *px = reinterpret_cast<const float4 *>(swx[tcx]);
+                const float4 *py = reinterpret_cast<const float4 *>(swy[tcy]);
+                for (int q = 0; q < (nk + 3) / 4; ++q) {
+                    const float4 a = px[q], b = py[q];
+                    const float v0 = a.x * b.x, v1 = a.y * b.y, v2 = a.z * b.z, v3 = a.w * b.w;
+                    if (ACC64) {
+                        acc64 += (double)v0;
+                        acc64 += (double)v1;
+                        acc64 += (double)v2;
+                        acc64 += (double)v3;
+                    } else {
+                        acc32 += v0;
+                        acc32 += v1;
+                        acc32 += v2;
+                        acc32 += v3;
+                    }
                 }
                 __syncthreads();
             }

@@ -43,18 +43,18 @@ __device__ inline void axis_weights(float d, float sg, int H, float scale, float
 
 
 // The same weights, written aligned to a tile edge of TWD pixels: window
-// pixel m (0 .. 2H) lands in w16[off + m] when that is inside the tile,
-// every other entry is 0.  The window sum is taken
+// pixel m (0 .. 2H) lands in w16[(off + m) * STRIDE] when off + m is inside
+// the tile, every other entry is 0.  The window sum is taken
 // from the two outer edges first, so each weight is stored once, already
 // scaled; the values are bit-identical to axis_weights().
-template <int TWD = 16>
+template <int TWD = 16, int STRIDE = 1>
 __device__ inline void axis_weights_tile(float d, float sg, int H, float scale, int off,
                                          float *w16)
 {
     const float r = 0.70710678118654752f;
     float inv = 1.0f / sg;
 #pragma unroll
-    for (int c = 0; c < TWD; ++c) w16[c] = 0.0f;
+    for (int c = 0; c < TWD; ++c) w16[c * STRIDE] = 0.0f;
     const float c0 = 0.5f * erfcf(fabsf(((float)(0 - H) - 0.5f - d) * inv) * r);
     const float clast = 0.5f * erfcf(fabsf(((float)(2 * H + 1 - H) - 0.5f - d) * inv) * r);
     const float f = scale / ((1.0f - c0) - clast);
@@ -74,7 +74,7 @@ __device__ inline void axis_weights_tile(float d, float sg, int H, float scale, 
         if (pprev) v = cprev - c;
         else if (!pos) v = c - cprev;
         else v = (1.0f - cprev) - c;
-        w16[off + m - 1] = v * f;
+        w16[(off + m - 1) * STRIDE] = v * f;
         cprev = c;
         pprev = pos;
     }
