@@ -7,25 +7,29 @@
 //
 // Positions are FP64; the CDF differences are evaluated in FP32 on
 // pixel-relative offsets (|offset| <= H + 1), each edge through one erfc on
-// the side of the distribution where nothing cancels.  One workgroup owns a
-// 16 x 16 tile, stages 256 samples' per-axis weights in LDS, aligned to the
-// tile's columns and rows (zero outside each window), and lets each thread
-// add its pixel's products in sample order (FP64 sums of FP32 partials over
-// four consecutive samples, or FP32 sums), so the result is deterministic and
-// written once.
+// the side of the distribution where nothing cancels.  One workgroup of 128
+// threads owns a 16 x 16 tile and stages 128 samples' per-axis weights in
+// LDS at a time, aligned to the tile's columns and rows (zero outside each
+// window).  Each thread adds the products of two pixels of one column (rows r
+// and r + 8, sharing the column's weight reads) in sample order (FP64 sums of
+// FP32 partials over four consecutive samples, or FP32 sums), so the result
+// is deterministic and written once.
 #include "psf_gauss.h"
 
 namespace e2e {
 
 namespace {
 
-constexpr int kChunk = 256;
+constexpr int kChunk = 128;    // samples staged together, one per thread
+constexpr int kThreads = 128;  // two waves; a thread adds two pixels
+static_assert(kChunk == kThreads && kThreads * 2 == kSepTile * kSepTile,
+              "one staged sample per thread, two pixels per thread");
 
 template <int DX, int DY, typename ST, bool SEP, bool ACC64>
-__global__ __launch_bounds__(256) void k_render_sep(const FrameDev *__restrict__ frames,
-                                                    const int2 *__restrict__ work, int n_work,
-                                                    int *__restrict__ counter,
-                                                    int *__restrict__ err)
+__global__ __launch_bounds__(kThreads) void k_render_sep(const FrameDev *__restrict__ frames,
+                                                         const int2 *__restrict__ work,
+                                                         int n_work, int *__restrict__ counter,
+                                                         int *__restrict__ err)
 {
     constexpr int TS = kSepTile;
     static_assert(TS == 16, "tile-aligned weights are 16 wide");
@@ -83,9 +87,11 @@ __global__ __launch_bounds__(256) void k_render_sep(const FrameDev *__restrict__
         }
         __syncthreads();
         const int count = uniform_i(sh_count);
-        const int pi = X0 + (tid % TS), pj = Y0 + (tid / TS);
-        double acc64 = 0.0;
-        float acc32 = 0.0f;
+        // two pixels per thread, rows tcy and tcy + 8 of column tcx
+        const int tcx = tid % TS, tcy = tid / TS;
+        const int pi = X0 + tcx, pj = Y0 + tcy;
+        double acc64a = 0.0, acc64b = 0.0;
+        float acc32a = 0.0f, acc32b = 0.0f;
 
         for (int li = 0; li < count; ++li) {
             const int tr = uniform_i(tlist[li]);
@@ -130,31 +136,42 @@ __global__ __launch_bounds__(256) void k_render_sep(const FrameDev *__restrict__
                 // every staged sample in order (four per 16-byte read); outside
                 // its window both weights' product is 0 and leaves the sum
                 // unchanged
-                const int tcx = tid % TS, tcy = tid / TS;
                 const float4 *px = reinterpret_cast<const float4 *>(swx[tcx]);
-                const float4 *py = reinterpret_cast<const float4 *>(swy[tcy]);
+                const float4 *pya = reinterpret_cast<const float4 *>(swy[tcy]);
+                const float4 *pyb = reinterpret_cast<const float4 *>(swy[tcy + 8]);
                 for (int q = 0; q < (nk + 3) / 4; ++q) {
-                    const float4 a = px[q], b = py[q];
+                    const float4 a = px[q], b = pya[q], c = pyb[q];
                     const float v0 = a.x * b.x, v1 = a.y * b.y, v2 = a.z * b.z, v3 = a.w * b.w;
+                    const float u0 = a.x * c.x, u1 = a.y * c.y, u2 = a.z * c.z, u3 = a.w * c.w;
                     if (ACC64) {
                         // four non-negative products summed in FP32 (relative
                         // error <= 3 ulp of the partial), the partials in FP64
-                        acc64 += (double)(((v0 + v1) + v2) + v3);
+                        acc64a += (double)(((v0 + v1) + v2) + v3);
+                        acc64b += (double)(((u0 + u1) + u2) + u3);
                     } else {
-                        acc32 += v0;
-                        acc32 += v1;
-                        acc32 += v2;
-                        acc32 += v3;
+                        acc32a += v0;
+                        acc32a += v1;
+                        acc32a += v2;
+                        acc32a += v3;
+                        acc32b += u0;
+                        acc32b += u1;
+                        acc32b += u2;
+                        acc32b += u3;
                     }
                 }
                 __syncthreads();
             }
         }
-        if (pi < F.nx && pj < F.ny) {
-            double v = ACC64 ? acc64 : (double)acc32;
-            size_t o = (size_t)pj * F.nx + pi;
-            if (F.out_f64) ((double *)F.out)[o] = v;
-            else ((float *)F.out)[o] = (float)v;
+        if (pi < F.nx) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int row = pj + 8 * h;
+                if (row >= F.ny) continue;
+                double v = ACC64 ? (h ? acc64b : acc64a) : (double)(h ? acc32b : acc32a);
+                size_t o = (size_t)row * F.nx + pi;
+                if (F.out_f64) ((double *)F.out)[o] = v;
+                else ((float *)F.out)[o] = (float)v;
+            }
         }
         __syncthreads();
     }
@@ -168,17 +185,17 @@ hipError_t launch_st(const FrameDev *frames_dev, const KernelCfg &cfg, bool sep,
     bool acc64 = cfg.precision != E2E_PREC_F32;
     if (sep) {
         if (acc64)
-            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, true, true>), dim3(nb), dim3(256), 0,
+            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, true, true>), dim3(nb), dim3(kThreads), 0,
                                s, frames_dev, work, n_work, counter, err);
         else
-            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, true, false>), dim3(nb), dim3(256), 0,
+            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, true, false>), dim3(nb), dim3(kThreads), 0,
                                s, frames_dev, work, n_work, counter, err);
     } else {
         if (acc64)
-            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, false, true>), dim3(nb), dim3(256), 0,
+            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, false, true>), dim3(nb), dim3(kThreads), 0,
                                s, frames_dev, work, n_work, counter, err);
         else
-            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, false, false>), dim3(nb), dim3(256),
+            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, false, false>), dim3(nb), dim3(kThreads),
                                0, s, frames_dev, work, n_work, counter, err);
     }
     return hipGetLastError();
@@ -201,7 +218,8 @@ hipError_t launch_deg(const FrameDev *frames_dev, const KernelCfg &cfg, bool sep
 hipError_t launch_sep(const FrameDev *frames_dev, const KernelCfg &cfg, const int2 *work,
                       int n_work, int *counter, int *err, hipStream_t s)
 {
-    int nb = work == nullptr ? cfg.plain_tiles : (n_work < 1024 ? n_work : 1024);
+    // persistent launches: 2048 two-wave workgroups, 8 waves per CU
+    int nb = work == nullptr ? cfg.plain_tiles : (n_work < 2048 ? n_work : 2048);
     if (nb <= 0) return hipSuccess;
     bool sep = cfg.kw != 0;
     if (cfg.degx <= 3 && cfg.degy <= 2)
