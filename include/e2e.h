@@ -74,7 +74,8 @@ typedef uint64_t e2e_ticket;
 
 /* arithmetic of the render path */
 #define E2E_PREC_F64 0       /* FP64 positions, FP32 PSF offsets, FP64 sums    */
-#define E2E_PREC_F32 1       /* separable only: FP32 weights and FP32 sums     */
+#define E2E_PREC_F32 1       /* separable only: FP32 weights (fitted normal
+                                tail, Numerical Recipes Sec. 6.2) and FP32 sums */
 #define E2E_PREC_BF16_HILO 2 /* separable only: bf16 hi/lo MFMA, FP32 sums     */
 #define E2E_PREC_F16_HILO 3  /* separable only: fp16 hi/lo MFMA, FP32 sums     */
 

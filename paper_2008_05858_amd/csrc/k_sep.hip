@@ -7,7 +7,8 @@
 //
 // Positions are FP64; the CDF differences are evaluated in FP32 on
 // pixel-relative offsets (|offset| <= H + 1), each edge through one erfc on
-// the side of the distribution where nothing cancels.  One workgroup of 128
+// the side of the distribution where nothing cancels (library erfcf; the
+// FP32 variant uses a fitted FP32 normal tail).  One workgroup of 128
 // threads owns a 16 x 16 tile and stages 128 samples' per-axis weights in
 // LDS at a time, aligned to the tile's columns and rows (zero outside each
 // window).  Each thread adds the products of two pixels of one column (rows r
@@ -121,10 +122,11 @@ __global__ __launch_bounds__(kThreads) void k_render_sep(const FrameDev *__restr
                         sgx = sgy = (float)F.sigma;
                     }
                     float phi = (float)spec_at(spec, k) * scale;
-                    axis_weights_tile<TS, RS>((float)(x - axd), sgx, H, phi,
-                                              (int)axd - H - X0, &swx[0][tid]);
-                    axis_weights_tile<TS, RS>((float)(y - ayd), sgy, H, 1.0f,
-                                              (int)ayd - H - Y0, &swy[0][tid]);
+                    // the FP32 variant takes the FP32 fitted normal tail
+                    axis_weights_tile<TS, RS, !ACC64>((float)(x - axd), sgx, H, phi,
+                                                      (int)axd - H - X0, &swx[0][tid]);
+                    axis_weights_tile<TS, RS, !ACC64>((float)(y - ayd), sgy, H, 1.0f,
+                                                      (int)ayd - H - Y0, &swy[0][tid]);
                 } else {
 #pragma unroll
                     for (int c = 0; c < TS; ++c) {

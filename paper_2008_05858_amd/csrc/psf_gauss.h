@@ -42,33 +42,64 @@ __device__ inline void axis_weights(float d, float sg, int H, float scale, float
 }
 
 
+// Normal tail Phi(-|z|) = erfc(|z| / sqrt 2) / 2 in FP32, branch free: the
+// Chebyshev-fitted form erfc(x) = t exp(-x^2 + P(t)), t = 1 / (1 + x/2)
+// (Numerical Recipes, Press et al., 2nd ed., Sec. 6.2; fractional error
+// below 1.2e-7 for x >= 0 in exact arithmetic), evaluated in FP32 with the
+// hardware reciprocal and base-2 exponential.  About 2e-7 absolute error in
+// Phi near z = 0 (P sums terms of order one), against erfcf's few ulp: used
+// by the FP32 precision variant only.
+__device__ __forceinline__ float phi_tail_f32(float z)
+{
+    const float x = fabsf(z) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, x, 1.0f));
+    float p = 0.17087277f;
+    p = fmaf(p, t, -0.82215223f);
+    p = fmaf(p, t, 1.48851587f);
+    p = fmaf(p, t, -1.13520398f);
+    p = fmaf(p, t, 0.27886807f);
+    p = fmaf(p, t, -0.18628806f);
+    p = fmaf(p, t, 0.09678418f);
+    p = fmaf(p, t, 0.37409196f);
+    p = fmaf(p, t, 1.00002368f);
+    p = fmaf(p, t, -1.26551223f);
+    return 0.5f * t * __builtin_amdgcn_exp2f(fmaf(-x, x, p) * 1.4426950408889634f);
+}
+
+// Phi(-|e|): library erfcf, or the FP32 fitted tail when FAST.
+template <bool FAST>
+__device__ __forceinline__ float normal_tail(float e)
+{
+    if (FAST) return phi_tail_f32(e);
+    return 0.5f * erfcf(fabsf(e) * 0.70710678118654752f);
+}
+
 // The same weights, written aligned to a tile edge of TWD pixels: window
 // pixel m (0 .. 2H) lands in w16[(off + m) * STRIDE] when off + m is inside
 // the tile, every other entry is 0.  The window sum is taken
 // from the two outer edges first, so each weight is stored once, already
 // scaled; the values are bit-identical to axis_weights().
-template <int TWD = 16, int STRIDE = 1>
+template <int TWD = 16, int STRIDE = 1, bool FAST = false>
 __device__ inline void axis_weights_tile(float d, float sg, int H, float scale, int off,
                                          float *w16)
 {
-    const float r = 0.70710678118654752f;
     float inv = 1.0f / sg;
 #pragma unroll
     for (int c = 0; c < TWD; ++c) w16[c * STRIDE] = 0.0f;
-    const float c0 = 0.5f * erfcf(fabsf(((float)(0 - H) - 0.5f - d) * inv) * r);
-    const float clast = 0.5f * erfcf(fabsf(((float)(2 * H + 1 - H) - 0.5f - d) * inv) * r);
+    const float c0 = normal_tail<FAST>(((float)(0 - H) - 0.5f - d) * inv);
+    const float clast = normal_tail<FAST>(((float)(2 * H + 1 - H) - 0.5f - d) * inv);
     const float f = scale / ((1.0f - c0) - clast);
     float cprev = c0;
     bool pprev = false;  // the first edge lies left of the centre
     const int m0 = max(1, 1 - off), m1 = min(2 * H + 1, TWD - off);
     if (m0 > 1) {
         const float e = ((float)(m0 - 1 - H) - 0.5f - d) * inv;
-        cprev = 0.5f * erfcf(fabsf(e) * r);
+        cprev = normal_tail<FAST>(e);
         pprev = e >= 0.0f;
     }
     for (int m = m0; m <= m1; ++m) {
         const float e = ((float)(m - H) - 0.5f - d) * inv;
-        const float c = m == 2 * H + 1 ? clast : 0.5f * erfcf(fabsf(e) * r);
+        const float c = m == 2 * H + 1 ? clast : normal_tail<FAST>(e);
         const bool pos = e >= 0.0f;
         float v;
         if (pprev) v = cprev - c;
