@@ -77,8 +77,9 @@ __device__ __forceinline__ float normal_tail(float e)
 // The same weights, written aligned to a tile edge of TWD pixels: window
 // pixel m (0 .. 2H) lands in w16[(off + m) * STRIDE] when off + m is inside
 // the tile, every other entry is 0.  The window sum is taken
-// from the two outer edges first, so each weight is stored once, already
-// scaled; the values are bit-identical to axis_weights().
+// from the two outer edges first (through the fitted tail, see below), so
+// each weight is stored once, already scaled; the other edges are as in
+// axis_weights() (erfcf unless FAST).
 template <int TWD = 16, int STRIDE = 1, bool FAST = false>
 __device__ inline void axis_weights_tile(float d, float sg, int H, float scale, int off,
                                          float *w16)
