@@ -8,32 +8,36 @@
 // Positions are FP64; the CDF differences are evaluated in FP32 on
 // pixel-relative offsets (|offset| <= H + 1), each edge through one erfc on
 // the side of the distribution where nothing cancels (library erfcf; the
-// FP32 variant uses a fitted FP32 normal tail).  One workgroup of 128
-// threads owns a 16 x 16 tile and stages 128 samples' per-axis weights in
-// LDS at a time, aligned to the tile's columns and rows (zero outside each
-// window).  Each thread adds the products of two pixels of one column (rows r
-// and r + 8, sharing the column's weight reads) in sample order (FP64 sums of
-// FP32 partials over four consecutive samples, or FP32 sums), so the result
-// is deterministic and written once.
+// FP32 variant uses a fitted FP32 normal tail).  One workgroup owns a 16 x 16
+// tile and stages one sample's per-axis weights per thread in LDS, aligned
+// to the tile's columns and rows (zero outside each window).  Each thread
+// adds the products of one or two pixels of one column in sample order (FP64
+// sums of FP32 partials over four consecutive samples, or FP32 sums), so the
+// result is deterministic and written once.
 #include "psf_gauss.h"
 
 namespace e2e {
 
 namespace {
 
-constexpr int kChunk = 128;    // samples staged together, one per thread
-constexpr int kThreads = 128;  // two waves; a thread adds two pixels
-static_assert(kChunk == kThreads && kThreads * 2 == kSepTile * kSepTile,
-              "one staged sample per thread, two pixels per thread");
+// NP pixels per thread (rows tcy + (16 / NP) j of column tcx), 256 / NP
+// threads per tile, as many samples staged together, one per thread.  Large
+// frames take NP = 2 (the column's weight read shared by two pixels), small
+// ones NP = 1 (twice the waves per tile, half the chunks: lower latency).
+// Both add every pixel's products in the same groups of four consecutive
+// samples, so they give the same bits.
+constexpr int kSepSmallTiles = 16384;
 
-template <int DX, int DY, typename ST, bool SEP, bool ACC64>
-__global__ __launch_bounds__(kThreads) void k_render_sep(const FrameDev *__restrict__ frames,
+template <int DX, int DY, typename ST, bool SEP, bool ACC64, int NP>
+__global__ __launch_bounds__(256 / NP) void k_render_sep(const FrameDev *__restrict__ frames,
                                                          const int2 *__restrict__ work,
                                                          int n_work, int *__restrict__ counter,
                                                          int *__restrict__ err)
 {
     constexpr int TS = kSepTile;
     static_assert(TS == 16, "tile-aligned weights are 16 wide");
+    static_assert(NP == 1 || NP == 2, "one or two pixels per thread");
+    constexpr int kChunk = 256 / NP;
     // per staged sample, its weights on the tile's 16 columns / 16 rows
     // (zero outside its window), stored column-major ([pixel][sample]) so a
     // thread reads four consecutive samples' weights in one 16-byte load
@@ -88,11 +92,15 @@ __global__ __launch_bounds__(kThreads) void k_render_sep(const FrameDev *__restr
         }
         __syncthreads();
         const int count = uniform_i(sh_count);
-        // two pixels per thread, rows tcy and tcy + 8 of column tcx
         const int tcx = tid % TS, tcy = tid / TS;
         const int pi = X0 + tcx, pj = Y0 + tcy;
-        double acc64a = 0.0, acc64b = 0.0;
-        float acc32a = 0.0f, acc32b = 0.0f;
+        double acc64[NP];
+        float acc32[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            acc64[j] = 0.0;
+            acc32[j] = 0.0f;
+        }
 
         for (int li = 0; li < count; ++li) {
             const int tr = uniform_i(tlist[li]);
@@ -139,26 +147,24 @@ __global__ __launch_bounds__(kThreads) void k_render_sep(const FrameDev *__restr
                 // its window both weights' product is 0 and leaves the sum
                 // unchanged
                 const float4 *px = reinterpret_cast<const float4 *>(swx[tcx]);
-                const float4 *pya = reinterpret_cast<const float4 *>(swy[tcy]);
-                const float4 *pyb = reinterpret_cast<const float4 *>(swy[tcy + 8]);
                 for (int q = 0; q < (nk + 3) / 4; ++q) {
-                    const float4 a = px[q], b = pya[q], c = pyb[q];
-                    const float v0 = a.x * b.x, v1 = a.y * b.y, v2 = a.z * b.z, v3 = a.w * b.w;
-                    const float u0 = a.x * c.x, u1 = a.y * c.y, u2 = a.z * c.z, u3 = a.w * c.w;
-                    if (ACC64) {
-                        // four non-negative products summed in FP32 (relative
-                        // error <= 3 ulp of the partial), the partials in FP64
-                        acc64a += (double)(((v0 + v1) + v2) + v3);
-                        acc64b += (double)(((u0 + u1) + u2) + u3);
-                    } else {
-                        acc32a += v0;
-                        acc32a += v1;
-                        acc32a += v2;
-                        acc32a += v3;
-                        acc32b += u0;
-                        acc32b += u1;
-                        acc32b += u2;
-                        acc32b += u3;
+                    const float4 a = px[q];
+#pragma unroll
+                    for (int j = 0; j < NP; ++j) {
+                        const float4 b =
+                            reinterpret_cast<const float4 *>(swy[tcy + (TS / NP) * j])[q];
+                        const float v0 = a.x * b.x, v1 = a.y * b.y, v2 = a.z * b.z,
+                                    v3 = a.w * b.w;
+                        if (ACC64) {
+                            // four non-negative products summed in FP32 (relative
+                            // error <= 3 ulp of the partial), the partials in FP64
+                            acc64[j] += (double)(((v0 + v1) + v2) + v3);
+                        } else {
+                            acc32[j] += v0;
+                            acc32[j] += v1;
+                            acc32[j] += v2;
+                            acc32[j] += v3;
+                        }
                     }
                 }
                 __syncthreads();
@@ -166,10 +172,10 @@ __global__ __launch_bounds__(kThreads) void k_render_sep(const FrameDev *__restr
         }
         if (pi < F.nx) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int row = pj + 8 * h;
+            for (int j = 0; j < NP; ++j) {
+                const int row = pj + (TS / NP) * j;
                 if (row >= F.ny) continue;
-                double v = ACC64 ? (h ? acc64b : acc64a) : (double)(h ? acc32b : acc32a);
+                double v = ACC64 ? acc64[j] : (double)acc32[j];
                 size_t o = (size_t)row * F.nx + pi;
                 if (F.out_f64) ((double *)F.out)[o] = v;
                 else ((float *)F.out)[o] = (float)v;
@@ -179,38 +185,49 @@ __global__ __launch_bounds__(kThreads) void k_render_sep(const FrameDev *__restr
     }
 }
 
-template <int DX, int DY, typename ST>
-hipError_t launch_st(const FrameDev *frames_dev, const KernelCfg &cfg, bool sep,
-                     const int2 *work, int n_work, int *counter, int *err, int nb,
-                     hipStream_t s)
+template <int DX, int DY, typename ST, int NP>
+hipError_t launch_np(const FrameDev *frames_dev, bool acc64, bool sep, const int2 *work,
+                     int n_work, int *counter, int *err, hipStream_t s)
 {
-    bool acc64 = cfg.precision != E2E_PREC_F32;
+    // plain: one workgroup per tile; persistent: 4096 waves, 16 per CU
+    constexpr int NT = 256 / NP;
+    const int cap = 2048 * 256 / (NT * 2);
+    const int nb = work == nullptr ? n_work : (n_work < cap ? n_work : cap);
     if (sep) {
         if (acc64)
-            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, true, true>), dim3(nb), dim3(kThreads), 0,
+            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, true, true, NP>), dim3(nb), dim3(NT), 0,
                                s, frames_dev, work, n_work, counter, err);
         else
-            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, true, false>), dim3(nb), dim3(kThreads), 0,
-                               s, frames_dev, work, n_work, counter, err);
+            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, true, false, NP>), dim3(nb), dim3(NT),
+                               0, s, frames_dev, work, n_work, counter, err);
     } else {
         if (acc64)
-            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, false, true>), dim3(nb), dim3(kThreads), 0,
-                               s, frames_dev, work, n_work, counter, err);
+            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, false, true, NP>), dim3(nb), dim3(NT),
+                               0, s, frames_dev, work, n_work, counter, err);
         else
-            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, false, false>), dim3(nb), dim3(kThreads),
+            hipLaunchKernelGGL((k_render_sep<DX, DY, ST, false, false, NP>), dim3(nb), dim3(NT),
                                0, s, frames_dev, work, n_work, counter, err);
     }
     return hipGetLastError();
 }
 
+template <int DX, int DY, typename ST>
+hipError_t launch_st(const FrameDev *frames_dev, const KernelCfg &cfg, bool sep,
+                     const int2 *work, int n_items, int *counter, int *err, hipStream_t s)
+{
+    const bool acc64 = cfg.precision != E2E_PREC_F32;
+    if (n_items < kSepSmallTiles)
+        return launch_np<DX, DY, ST, 1>(frames_dev, acc64, sep, work, n_items, counter, err, s);
+    return launch_np<DX, DY, ST, 2>(frames_dev, acc64, sep, work, n_items, counter, err, s);
+}
+
 template <int DX, int DY>
 hipError_t launch_deg(const FrameDev *frames_dev, const KernelCfg &cfg, bool sep,
-                      const int2 *work, int n_work, int *counter, int *err, int nb,
-                      hipStream_t s)
+                      const int2 *work, int n_items, int *counter, int *err, hipStream_t s)
 {
     if (cfg.spec_f64)
-        return launch_st<DX, DY, double>(frames_dev, cfg, sep, work, n_work, counter, err, nb, s);
-    return launch_st<DX, DY, float>(frames_dev, cfg, sep, work, n_work, counter, err, nb, s);
+        return launch_st<DX, DY, double>(frames_dev, cfg, sep, work, n_items, counter, err, s);
+    return launch_st<DX, DY, float>(frames_dev, cfg, sep, work, n_items, counter, err, s);
 }
 
 }  // namespace
@@ -220,15 +237,15 @@ hipError_t launch_deg(const FrameDev *frames_dev, const KernelCfg &cfg, bool sep
 hipError_t launch_sep(const FrameDev *frames_dev, const KernelCfg &cfg, const int2 *work,
                       int n_work, int *counter, int *err, hipStream_t s)
 {
-    // persistent launches: 2048 two-wave workgroups, 8 waves per CU
-    int nb = work == nullptr ? cfg.plain_tiles : (n_work < 2048 ? n_work : 2048);
-    if (nb <= 0) return hipSuccess;
+    // tiles of the plain launch, or work items of the persistent one
+    const int n_items = work == nullptr ? cfg.plain_tiles : n_work;
+    if (n_items <= 0) return hipSuccess;
     bool sep = cfg.kw != 0;
     if (cfg.degx <= 3 && cfg.degy <= 2)
-        return launch_deg<3, 2>(frames_dev, cfg, sep, work, n_work, counter, err, nb, s);
+        return launch_deg<3, 2>(frames_dev, cfg, sep, work, n_items, counter, err, s);
     if (cfg.degx <= 4 && cfg.degy <= 3)
-        return launch_deg<4, 3>(frames_dev, cfg, sep, work, n_work, counter, err, nb, s);
-    return launch_deg<7, 7>(frames_dev, cfg, sep, work, n_work, counter, err, nb, s);
+        return launch_deg<4, 3>(frames_dev, cfg, sep, work, n_items, counter, err, s);
+    return launch_deg<7, 7>(frames_dev, cfg, sep, work, n_items, counter, err, s);
 }
 
 }  // namespace e2e

@@ -92,3 +92,20 @@ def test_c4_hires_sampled():
     print("case c4 HIRES-shaped full frame", flush=True)
     g = _gu().render(sc, rq)
     assert _check("c4", sc, rq, g, n_bright=12, n_rand=4, seed=9) < TOL
+
+
+def test_separable_one_and_two_pixel_kernels_agree_bitwise():
+    """Small launches of the separable kernel run one pixel per thread, large
+    ones two; both add each pixel's products in the same groups of four
+    samples, so a frame gets the same bits from either."""
+    from paper_2008_05858_amd import Loaded
+    gu = _gu()
+    small, big = scene("mini_sep"), scene("c2")
+    ls, lb = Loaded(gu.ctx(), small), Loaded(gu.ctx(), big)
+    rq = Request(rv_mps=1.25)
+    print("case mini_sep alone (one pixel per thread) vs batched with c2 (two)", flush=True)
+    alone = gu.render(small, rq, loaded=ls)
+    outs = gu.render_batch([small, big], [rq, Request(rv_mps=2.0)], [ls, lb])
+    assert np.array_equal(alone, outs[0])
+    ls.free()
+    lb.free()
