@@ -101,7 +101,7 @@ extern "C" void e2e_destroy(e2e_ctx *ctx)
         delete kv.second;
     }
     for (auto &kv : ctx->psfs) {
-        hipFree(kv.second->tb);
+        hipFree(kv.second->tfrag);
         hipFree(kv.second->sxy);
         delete kv.second;
     }
@@ -266,6 +266,33 @@ static void node_taps(const float *K, int kw, double *tb)
                 tb[((size_t)s * OS + p) * DD + dd] = box(OS * dd - p, kw - 1 - s);
 }
 
+// The stencil of one node over a band of 4 deposit rows starting at phase C
+// (rows C .. C + 3 of a 4-row pixel period) is the matrix
+//   T_C[k = (s, r)][j] = tb[s][(C + r) mod 4][j - floor((C + r) / 4)]
+// (zero outside 0 <= that row offset < DD and for padded s).  Stored per
+// output row j as the fragments v_mfma_f32_16x16x32_f16 reads (eight
+// consecutive k = two slot offsets x four band rows), scaled by 2^kTapShift
+// and split into fp16 hi + lo parts (the FP64 tap to about 2^-22 relative).
+static void node_frags(const double *tb, int kw, uint16_t *out)
+{
+    const int NS = kw + kOS - 1, DD = table_dd(kw), NJ = DD + 1;
+    const int NFR = table_frag_rows(kw), SP = table_slots_padded(kw), FRS = table_frag_row(kw);
+    for (int C = 0; C < 4; ++C)
+        for (int j = 0; j < NFR; ++j)
+            for (int s = 0; s < SP; ++s)
+                for (int r = 0; r < 4; ++r) {
+                    double v = 0.0;
+                    const int w = C + r, dd = j - (w >> 2);
+                    if (j < NJ && s < NS && dd >= 0 && dd < DD)
+                        v = std::ldexp(tb[((size_t)s * kOS + (w & 3)) * DD + dd], kTapShift);
+                    const _Float16 hi = (_Float16)v;
+                    const _Float16 lo = (_Float16)(v - (double)hi);
+                    const size_t o = ((size_t)C * NFR + j) * FRS + (size_t)s * 4 + r;
+                    out[o] = __builtin_bit_cast(uint16_t, hi);
+                    out[(size_t)4 * NFR * FRS + o] = __builtin_bit_cast(uint16_t, lo);
+                }
+}
+
 // Gauss-Legendre rule of n points on [-1, 1]: Newton's method on P_n from
 // the asymptotic guesses cos(pi (4i - 1) / (4n + 2)), P_n and P_n' by the
 // three-term recurrence; weights 2 / ((1 - x^2) P_n'(x)^2).
@@ -305,6 +332,7 @@ extern "C" e2e_status e2e_psf_load(e2e_ctx *ctx, const e2e_psf_desc *d, e2e_psf_
     P->kh = d->kh;
     P->os = d->oversample;
     std::vector<double> tb;
+    std::vector<uint16_t> frag;
     std::vector<float> sxy, sfq;
     auto bad = [&](e2e_status c, const char *m) {
         delete P;
@@ -372,7 +400,8 @@ extern "C" e2e_status e2e_psf_load(e2e_ctx *ctx, const e2e_psf_desc *d, e2e_psf_
         size_t ksz = (size_t)d->kw * d->kh, nodes = (size_t)d->grid_nx * d->grid_ny;
         const int NS = d->kw + kOS - 1, DD = (d->kw + kOS - 2) / kOS + 1;
         size_t node = (size_t)kOS * NS * DD;
-        tb.resize(node * nodes);
+        tb.resize(node);
+        frag.resize((size_t)table_frag_node(d->kw) * nodes);
         for (size_t q = 0; q < nodes; ++q) {
             const float *K = d->tables + q * ksz;
             double s = 0;
@@ -384,21 +413,22 @@ extern "C" e2e_status e2e_psf_load(e2e_ctx *ctx, const e2e_psf_desc *d, e2e_psf_
                 delete P;
                 return fail(E2E_EPSF, "e2e_psf_load: node %zu sums to %.9g, not 1", q, s);
             }
-            node_taps(K, d->kw, tb.data() + q * node);
+            node_taps(K, d->kw, tb.data());
+            node_frags(tb.data(), d->kw, frag.data() + q * table_frag_node(d->kw));
         }
     } else {
         return bad(E2E_EINVAL, "unknown PSF kind");
     }
     hipSetDevice(ctx->dev);
-    std::vector<float> tbf(tb.begin(), tb.end());
-    size_t bytes = (tbf.size() + sxy.size() + sfq.size()) * sizeof(float);
+    size_t bytes = frag.size() * sizeof(uint16_t) + (sxy.size() + sfq.size()) * sizeof(float);
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (ctx->used + bytes > ctx->budget) return bad(E2E_ENOMEM, "tables exceed the HBM budget");
     hipError_t e = hipSuccess;
-    if (!tbf.empty()) {
-        e = hipMalloc(&P->tb, tbf.size() * sizeof(float));
+    if (!frag.empty()) {
+        e = hipMalloc(&P->tfrag, frag.size() * sizeof(uint16_t));
         if (e == hipSuccess)
-            e = hipMemcpy(P->tb, tbf.data(), tbf.size() * sizeof(float), hipMemcpyHostToDevice);
+            e = hipMemcpy(P->tfrag, frag.data(), frag.size() * sizeof(uint16_t),
+                          hipMemcpyHostToDevice);
     }
     if (e == hipSuccess && !sxy.empty()) {
         e = hipMalloc(&P->sxy, sxy.size() * sizeof(float));
@@ -411,7 +441,7 @@ extern "C" e2e_status e2e_psf_load(e2e_ctx *ctx, const e2e_psf_desc *d, e2e_psf_
             e = hipMemcpy(P->sfq, sfq.data(), sfq.size() * sizeof(float), hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
-        hipFree(P->tb);
+        hipFree(P->tfrag);
         hipFree(P->sxy);
         hipFree(P->sfq);
         delete P;
@@ -452,7 +482,7 @@ extern "C" e2e_status e2e_psf_free(e2e_ctx *ctx, e2e_psf_id id)
     if (it->second->refs > 0) return fail(E2E_EBUSY, "psf %llu in use", (unsigned long long)id);
     hipSetDevice(ctx->dev);
     hipDeviceSynchronize();
-    hipFree(it->second->tb);
+    hipFree(it->second->tfrag);
     hipFree(it->second->sxy);
     hipFree(it->second->sfq);
     ctx->used -= it->second->bytes;
@@ -681,7 +711,7 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
             sc->temps.push_back(dev_out[i]);
         }
         F.out = dev_out[i];
-        F.tb = P->tb;
+        F.tfrag = P->tfrag;
         F.sxy = P->sxy;
         F.sfq = P->sfq;
         F.sfi_R = P->sfi_R;

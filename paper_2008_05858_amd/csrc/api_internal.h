@@ -29,7 +29,7 @@ struct PsfRes {
     int kind = 0;
     double sigma = 0;
     int H = 0, gx = 1, gy = 1, kw = 0, kh = 0, os = 0;
-    float *tb = nullptr;    // table taps (FP32)
+    uint16_t *tfrag = nullptr;  // table taps as fp16 hi/lo product fragments
     float *sxy = nullptr;   // separable sigma grid
     float *sfq = nullptr;   // SFI: quadrature nodes [R][3]
     int sfi_R = 0, sfi_S = 0, sfi_shape = 0;

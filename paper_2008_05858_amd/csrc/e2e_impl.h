@@ -23,6 +23,26 @@ constexpr int kSfiMaxR = 16;     // SFI: quadrature node pairs (32 nodes)
 constexpr int kSfiMaxH = 7;      // SFI: footprint half width
 constexpr int kSfiTW = 64;       // SFI tile width (x)
 constexpr int kSfiTH = 32;       // SFI tile height (y)
+constexpr int kTapShift = 8;     // table taps are stored times 2^8 in their fp16 fragments
+
+// Table path: the stencil of one node layer over a band of 4 deposit rows is
+// a product with k = (slot offset s, band row r), s padded to a multiple of 8
+// so k runs in steps of 32 (v_mfma_f32_16x16x32_f16).
+constexpr __host__ __device__ int table_dd(int kw) { return (kw + kOS - 2) / kOS + 1; }
+constexpr __host__ __device__ int table_slots_padded(int kw) { return (kw + kOS - 1 + 7) / 8 * 8; }
+constexpr __host__ __device__ int table_ksteps(int kw) { return table_slots_padded(kw) / 8; }
+// halfs of one row (one output row j of one band phase) of a tap fragment table:
+// [slot offset][band row]
+constexpr __host__ __device__ int table_frag_row(int kw) { return 4 * table_slots_padded(kw); }
+// rows per band phase: output rows 0 .. dd (dd + 1 of them), then a zero row
+constexpr __host__ __device__ int table_frag_rows(int kw) { return table_dd(kw) + 2; }
+// halfs of one node's fragments: [hi, lo][band phase][row][slot offset][band row]
+constexpr __host__ __device__ int table_frag_node(int kw)
+{
+    return 2 * 4 * table_frag_rows(kw) * table_frag_row(kw);
+}
+// slots of one band row in LDS: 64 pixel columns x 4, plus the widest read
+constexpr __host__ __device__ int table_band_slots(int kw) { return 4 * 64 + 8 * table_ksteps(kw); }
 
 // Device-resident record of one trace (spectral-format database row).
 struct TraceDev {
@@ -60,7 +80,7 @@ struct FrameDev {
     const TraceDev *tr;
     const void *const *spec;  // device array of device pointers, per slot
     void *out;
-    const float *tb;          // table path: FP32 taps [node][s][p][dd]
+    const void *tfrag;        // table path: fp16 tap fragments per node (table_frag_node)
     const float *sxy;         // separable / SFI: [gy][gx][2]
     const float *sfq;         // SFI: quadrature nodes [R][3] (a_p, h_p, w_p)
     SegDev *segs;             // [ntx][ntr]

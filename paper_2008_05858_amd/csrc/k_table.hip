@@ -17,14 +17,19 @@
 // tile (ascending trace order, then node cell) it
 //   1. gives each thread one slot column and finds that column's samples by
 //      a secant search on the FP64 format polynomial;
-//   2. walks those samples in order (spectrum values prefetched in groups,
+//   2. walks those samples in order (spectrum values read four at a time,
 //      FP64 positions, FP64 moment sums per row run) into the column's
 //      private 4-row deposit window held in registers;
-//   3. for each band of 3 deposit rows that holds data, lays the windows out
-//      as a dense band in LDS, and each wave applies the node stencils of a
-//      quarter of the slot offsets (FP32 taps streamed through the scalar
-//      cache, FP32 sums per node layer added into FP64); the four wave
-//      partials are added into the FP64 LDS tile in a fixed order.
+//   3. for each band of 4 consecutive deposit rows, stores the deposits of
+//      every slot column in LDS as fp16 hi + lo parts (scaled by a power of
+//      two), and applies the stencils as one dense product per node layer:
+//          out[i][j] = sum over (slot offset s, band row r) of
+//                      D[r][4 i + s] * T[s][phase(r)][j - offset(r)],
+//      i = pixel column, j = output row of the band.  Each wave owns one
+//      node layer and runs v_mfma_f32_16x16x32_f16 over 16-column blocks
+//      (hi*hi + hi*lo + lo*hi, FP32 accumulation); the tap fragments come
+//      pre-split from the table built at load time.  The four layer
+//      partials are added in FP64, in a fixed order, into the FP64 LDS tile.
 // The summation order is fixed, so reruns are bitwise identical.
 #include <type_traits>
 
@@ -35,8 +40,45 @@ namespace e2e {
 namespace {
 
 constexpr int kNone = 0x3fffffff;  // "no row yet"; far from any real row
-constexpr int kCand = 256;         // trace segments one run of tiles can hold
 constexpr int kUnf = 64;           // traces one tile can hand on to the next
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u4s __attribute__((ext_vector_type(4)));
+// four spectrum values (two for FP64), read at any 4-byte-aligned index
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+
+template <typename ST>
+struct SpecVec;
+template <>
+struct SpecVec<float> {
+    static constexpr int G = 4;
+    __device__ static void load(gptr<float> p, int k, int n, float v[4])
+    {
+        if (k + 4 <= n) {
+            const f4u q = *(const __attribute__((address_space(1))) f4u *)(p + k);
+            v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = k + e < n ? p[k + e] : 0.0f;
+        }
+    }
+};
+template <>
+struct SpecVec<double> {
+    static constexpr int G = 2;
+    __device__ static void load(gptr<double> p, int k, int n, double v[2])
+    {
+        if (k + 2 <= n) {
+            const d2u q = *(const __attribute__((address_space(1))) d2u *)(p + k);
+            v[0] = q.x; v[1] = q.y;
+        } else {
+            v[0] = k < n ? p[k] : 0.0;
+            v[1] = k + 1 < n ? p[k + 1] : 0.0;
+        }
+    }
+};
 
 template <int KW, int DX, int DY, typename ST>
 __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_table(
@@ -47,48 +89,50 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
     constexpr int NCOL = kTableThreads;        // slot columns per tile
     constexpr int TW = (NCOL - KW) / OS;       // tile width in pixels
     constexpr int TH = kTableTH;
-    constexpr int NS = KW + OS - 1;            // slots per pixel column
     constexpr int DD = (KW + OS - 2) / OS + 1; // pixel rows per deposit row
-    constexpr int NODE = OS * NS * DD;         // taps per node
+    constexpr int NJ = DD + 1;                 // output rows a band reaches
+    constexpr int NKS = table_ksteps(KW);      // k-steps of 32 per node layer
+    constexpr int RL = table_band_slots(KW);   // slots of a band row in LDS
+    constexpr int NFR = NJ + 1;                // tap-fragment rows per phase
+    constexpr int FRS = table_frag_row(KW);    // halfs per tap-fragment row
+    constexpr int KC = KW <= 32 ? 128 : 256;   // trace segments one run of tiles can hold
     constexpr double UC = 0.5 * (OS - KW);
     static_assert(OS * TW + KW == NCOL, "tile geometry");
-    static_assert(TW <= 64, "one wave spans the tile width");
+    static_assert(TW <= 64 && NJ <= 16, "one MFMA block of output rows, four of columns");
+    static_assert(4 * 63 + 2 * (4 * NKS - 1) + 2 <= RL, "band row covers the reads");
 
     constexpr int CR = 16;                     // carried rows below a tile
-    constexpr int NB = 3;                      // deposit rows per band
-    constexpr int NJ = DD + 1;                 // output rows a band reaches
-    constexpr int SQ = (NS + 3) / 4;           // slot offsets per wave
-    constexpr int PQ = 80;                     // phase block of a band row (bank spread)
-    constexpr int PR = 4 * PQ;                 // band row stride (floats)
-    constexpr int BANDF = 4 * NB * PR;         // floats of the band
-    constexpr int PARTF = 3 * NJ * 64 * 2;     // floats of the wave partials
-    constexpr int BUFF = BANDF > PARTF ? BANDF : PARTF;
-    static_assert(NB <= 4, "a band row range maps to two output offsets");
+    constexpr int XS = 17;                     // floats per column in the left-half exchange
+    constexpr int BANDB = 2 * 4 * RL * 8;      // bytes: [plane][layer][slot][4 rows] fp16
+    constexpr int PARTB = 4 * 4 * 64 * 16;     // bytes: [layer][m-block][lane] float4
+    constexpr int BUFB = BANDB > PARTB ? BANDB : PARTB;
+    static_assert(NCOL * XS * 4 <= BUFB, "the left-half exchange fits the band buffer");
 
-    // The band (4 node layers x NR rows x slots, slot c at (c & 3) * PQ + c / 4
-    // so a wave's stencil reads are consecutive) and, once the stencil has read
-    // it, the partial sums of waves 1..3.
-    __shared__ double bandbuf[BUFF / 2];
+    // The band (fp16 hi and lo planes of the 4 layers' deposits) and, once
+    // the products have read it, the four layers' FP32 partial outputs.
+    __shared__ __attribute__((aligned(16))) unsigned char bandbuf[BUFB];
     __shared__ double tile[TH][TW];
     __shared__ double carry[CR][TW];             // rows of the next tile
     __shared__ int unf[2][kUnf];                 // traces with rows beyond the carry
     __shared__ int sh_nunf[2];
-    __shared__ unsigned char tcont[kCand];       // item continues from the tile above
+    __shared__ unsigned char tcont[KC];          // item continues from the tile above
     __shared__ int kst[NCOL + 1];
-    __shared__ int ctr[kCand];                   // the run's trace segments: trace,
-    __shared__ SegDev cseg[kCand];               // segment record,
-    __shared__ TraceFrameDev cmeta[kCand];       // per-frame constants
-    __shared__ unsigned char tlist[kCand];       // this tile's items (candidate index)
-    __shared__ int sh_wsum[4], sh_item, sh_qmin, sh_qmax, sh_touch;
+    __shared__ int ctr[KC];                      // the run's trace segments: trace,
+    __shared__ SegDev cseg[KC];                  // segment record,
+    __shared__ TraceFrameDev cmeta[KC];          // per-frame constants
+    __shared__ unsigned char tlist[KC];          // this tile's items (candidate index)
+    __shared__ int sh_wsum[4], sh_item, sh_touch;
+    // per node-cell pass reductions, double-buffered by pass parity so a
+    // pass's reset cannot meet a slow wave's read of the previous pass
+    __shared__ int sh_qmin[2], sh_qmax[2];
+    __shared__ unsigned sh_dmax[2];
 
-    float *band = reinterpret_cast<float *>(bandbuf);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int clane = lane < TW ? lane : TW - 1;
+    const int l16 = lane & 15, lg = lane >> 4;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int pc = (tid & 3) * PQ + (tid >> 2);              // own slot in a band row
-    const int pcl = ((tid + NCOL - 1) & 3) * PQ + ((tid - 1) >> 2);  // slot tid - 1
     if (tid == 0) sh_touch = 0;
+    int cpar = 0;  // parity of the node-cell pass
 
     for (int iter = 0;; ++iter) {
         int fi, unit;
@@ -155,7 +199,7 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 if (!((bits >> j) & 1)) continue;
-                if (pos < kCand) {
+                if (pos < KC) {
                     ctr[pos] = mb + j;
                     cseg[pos] = sgv[j];
                     cmeta[pos] = Fp->tf[mb + j];
@@ -164,7 +208,7 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 }
                 ++pos;
             }
-            ncand = min(ncand + uniform_i(tot), kCand);
+            ncand = min(ncand + uniform_i(tot), KC);
             __syncthreads();
         }
 
@@ -261,12 +305,14 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
 
             for (int cyc = sg.cy0; cyc <= sg.cy1; ++cyc)
             for (int cxc = sg.cx0; cxc <= sg.cx1; ++cxc) {
+                cpar ^= 1;
                 cptr<TraceDev> Tp = as_const(Fp->tr) + tr;
                 double cxr[DX + 1], cyr[DY + 1];
 #pragma unroll
                 for (int j = 0; j <= DX; ++j) cxr[j] = Tp->cx[j];
 #pragma unroll
                 for (int j = 0; j <= DY; ++j) cyr[j] = Tp->cy[j];
+                const int nspec = Tp->n;
                 const double t0 = uniform_d(cmeta[ci].t0), dt = uniform_d(cmeta[ci].dt);
                 const double scale = uniform_d(cmeta[ci].scale);
                 gptr<ST> spec = as_global(uniform_ptr<ST>(cmeta[ci].spec));
@@ -275,7 +321,6 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 const double ua = fma(horner<DX>(cxr, fma((double)k0, dt, t0)), (double)OS, UC);
                 const double ub = fma(horner<DX>(cxr, fma((double)(k1 - 1), dt, t0)), (double)OS, UC);
                 const double inv_slope = ub > ua ? (double)(k1 - 1 - k0) / (ub - ua) : 0.0;
-
 
                 // ---- 1. samples of each slot column: first k with u(k) >= q
                 const int q = OS * X0 - KW + tid;
@@ -302,7 +347,11 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 };
                 kst[tid] = search(q);
                 if (tid == NCOL - 1) kst[NCOL] = search(q + 1);
-                if (tid == 0) { sh_qmin = 0x7fffffff; sh_qmax = -0x7fffffff; }
+                if (tid == 0) {
+                    sh_qmin[cpar] = 0x7fffffff;
+                    sh_qmax[cpar] = -0x7fffffff;
+                    sh_dmax[cpar] = 0u;
+                }
                 __syncthreads();
 
                 // ---- 2. this column's samples, in order.  Within one row run the
@@ -335,22 +384,8 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 int runQy = kNone, rb = kNone;
                 bool run_in = false;
                 int qmin = 0x7fffffff, qmax = -0x7fffffff;
-                // loop-local copies of the wave-uniform constants
-                double cxv[DX + 1], cyv[DY + 1];
-#pragma unroll
-                for (int j = 0; j <= DX; ++j) {
-                    cxv[j] = cxr[j];
-                    
-                }
-#pragma unroll
-                for (int j = 0; j <= DY; ++j) {
-                    cyv[j] = cyr[j];
-                    
-                }
-                double t0v = t0, dtv = dt, scv = scale, gsxv = gsx, gsyv = gsy;
-                
-                double ay0v = ay0, ay1v = ay1, fybv = fyb;
-                
+                double csum = 0.0;  // photons of the column (bounds its deposits)
+
                 auto flush = [&]() {
                     const int o = runQy - rb;
                     if (o < 0 || o > 2) {
@@ -361,7 +396,8 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                         qmin = min(qmin, runQy);
                         qmax = max(qmax, runQy);
                     }
-                    const double fya = fma(ay1v, ((double)runQy - UC) / OS, ay0v);
+                    csum += m[0][0];
+                    const double fya = fma(ay1, ((double)runQy - UC) / OS, ay0);
                     // polynomial coefficients (in rho) of cic x node weight
                     double X[2][2][3], Y[2][2][3];
                     auto coef = [](double a, double b, double c[2][2][3]) {
@@ -371,7 +407,7 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                         c[1][0][0] = 0.0;     c[1][0][1] = 1.0 - a;     c[1][0][2] = -b;
                     };
                     coef(fxa, fxb, X);
-                    coef(fya, fybv, Y);
+                    coef(fya, fyb, Y);
                     double Tm[2][2][3];
 #pragma unroll
                     for (int r = 0; r < 2; ++r)
@@ -392,7 +428,7 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                                 double d = fma(X[lr][nx][2], Tm[r][ny][2],
                                                fma(X[lr][nx][1], Tm[r][ny][1],
                                                    X[lr][nx][0] * Tm[r][ny][0]));
-                                dv[r] = (float)(d * scv);
+                                dv[r] = (float)(d * scale);
                             }
                             wr[l][lr][0] += o == 0 ? dv[0] : 0.0f;
                             wr[l][lr][1] += o == 0 ? dv[1] : (o == 1 ? dv[0] : 0.0f);
@@ -402,9 +438,9 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 };
                 const double UCq = UC - (double)q;
                 auto sample = [&](int k, double sv, auto mc) {
-                    double t = fma((double)k, dtv, t0v);
-                    double x = horner<DX>(cxv, t);
-                    double y = horner<DY>(cyv, t);
+                    double t = fma((double)k, dt, t0);
+                    double x = horner<DX>(cxr, t);
+                    double y = horner<DY>(cyr, t);
                     double rx = fma(x, (double)OS, UCq);
                     double vy = fma(y, (double)OS, UC);
                     double fly = floor(vy);
@@ -412,7 +448,7 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                     double ry = vy - fly;
                     bool in = true;
                     if constexpr (decltype(mc)::value)
-                        in = (ext_cell(x, gsxv, gxn) == cxc) & (ext_cell(y, gsyv, gyn) == cyc);
+                        in = (ext_cell(x, gsx, gxn) == cxc) & (ext_cell(y, gsy, gyn) == cyc);
                     double phi = in ? sv : 0.0;
                     if (Qy != runQy) {
                         if (runQy != kNone) {
@@ -438,47 +474,85 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                     m[2][1] = fma(e1, rx2, m[2][1]);
                     m[2][2] = fma(e2, rx2, m[2][2]);
                 };
-                const ST *specv = (const ST *)spec;
                 // a trace segment that stays in one node cell (the usual case)
                 // needs no per-sample cell test: two instances of the loop
                 auto walk = [&](auto mc) {
                     if (ks >= ke) return;
-                    // spectrum values four samples ahead (indices clamped into the
-                    // column, so every load is unconditional)
-                    gptr<ST> sp = as_global(specv);
-                    const int kl = ke - 1;
-                    ST v0 = sp[min(ks, kl)], v1 = sp[min(ks + 1, kl)];
-                    ST v2 = sp[min(ks + 2, kl)], v3 = sp[min(ks + 3, kl)];
-                    for (int kb = ks; kb < ke; kb += 4) {
-                        const ST n0 = sp[min(kb + 4, kl)], n1 = sp[min(kb + 5, kl)];
-                        const ST n2 = sp[min(kb + 6, kl)], n3 = sp[min(kb + 7, kl)];
-                        sample(kb, (double)v0, mc);
-                        if (kb + 1 < ke) sample(kb + 1, (double)v1, mc);
-                        if (kb + 2 < ke) sample(kb + 2, (double)v2, mc);
-                        if (kb + 3 < ke) sample(kb + 3, (double)v3, mc);
-                        v0 = n0; v1 = n1; v2 = n2; v3 = n3;
+                    // spectrum values G at a time (one 16-byte load per lane),
+                    // the next group's load issued before this group's samples
+                    constexpr int G = SpecVec<ST>::G;
+                    ST v[G], nv[G];
+                    SpecVec<ST>::load(spec, ks, nspec, v);
+                    for (int kb = ks; kb < ke; kb += G) {
+                        SpecVec<ST>::load(spec, min(kb + G, ke - 1), nspec, nv);
+#pragma unroll
+                        for (int e = 0; e < G; ++e)
+                            if (kb + e < ke) sample(kb + e, (double)v[e], mc);
+#pragma unroll
+                        for (int e = 0; e < G; ++e) v[e] = nv[e];
                     }
                     flush();
                 };
                 if (multi) walk(std::true_type());
                 else walk(std::false_type());
                 if (cyc == sg.cy1 && cxc == sg.cx1 && li + 1 < count) prefetch(li + 1);
+                // the left-slot halves belong to slot c - 1: hand them (and the
+                // window's first row) to the column on the left through LDS
+                float *xw = reinterpret_cast<float *>(bandbuf);
+#pragma unroll
+                for (int l = 0; l < 4; ++l)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) xw[tid * XS + l * 4 + r] = wr[l][0][r];
+                xw[tid * XS + 16] = __int_as_float(rb);
+                // column bound on any one deposit: all its photons
+                float cmax = (float)(csum * scale) * 1.0001f;
 #pragma unroll
                 for (int o = 32; o >= 1; o >>= 1) {
                     qmin = min(qmin, __shfl_xor(qmin, o));
                     qmax = max(qmax, __shfl_xor(qmax, o));
+                    cmax = fmaxf(cmax, __shfl_xor(cmax, o));
                 }
                 if (lane == 0 && qmin <= qmax) {
-                    atomicMin(&sh_qmin, qmin);
-                    atomicMax(&sh_qmax, qmax);
+                    atomicMin(&sh_qmin[cpar], qmin);
+                    atomicMax(&sh_qmax[cpar], qmax);
+                    atomicMax(&sh_dmax[cpar], __float_as_uint(cmax));
                 }
                 __syncthreads();
 
-                // ---- 3. stencils over bands of NB consecutive deposit rows
-                // (any start).  Deposit row 4n + p reaches output rows
-                // n .. n + DD - 1; a band starting at A spans output rows
-                // A/4 .. A/4 + NJ - 1.
-                const int qlo = uniform_i(sh_qmin), qhi = uniform_i(sh_qmax) + 1;
+                // ---- 3. stencils over bands of 4 consecutive deposit rows (any
+                // start).  Deposit row 4n + p reaches output rows n .. n + DD - 1;
+                // a band starting at A spans output rows A/4 .. A/4 + NJ - 1.
+                // slot c's deposits: its right-slot halves and column c + 1's
+                // left-slot halves.  Adjacent columns' first rows differ by at
+                // most one (|dy/dx| <= 1/2 over a quarter pixel), so slot c's
+                // rows fit a 5-row window from mrb.
+                float mw[4][5];
+                int mrb;
+                {
+                    const int nrb = tid + 1 < NCOL ? __float_as_int(xw[(tid + 1) * XS + 16]) : kNone;
+                    mrb = rb == kNone ? nrb : (nrb == kNone ? rb : min(rb, nrb));
+                    const int da = rb == kNone ? 8 : rb - mrb, dn = nrb == kNone ? 8 : nrb - mrb;
+                    if (da > 1 && da != 8) atomicOr(err, kErrRowWindow);
+                    if (dn > 1 && dn != 8) atomicOr(err, kErrRowWindow);
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        float nl[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            nl[r] = tid + 1 < NCOL ? xw[(tid + 1) * XS + l * 4 + r] : 0.0f;
+#pragma unroll
+                        for (int u = 0; u < 5; ++u) {
+                            float a = 0.0f, b = 0.0f;
+                            if (u < 4) a = da == 0 ? wr[l][1][u] : a;
+                            if (u >= 1) a = da == 1 ? wr[l][1][u - 1] : a;
+                            if (u < 4) b = dn == 0 ? nl[u] : b;
+                            if (u >= 1) b = dn == 1 ? nl[u - 1] : b;
+                            mw[l][u] = a + b;
+                        }
+                    }
+                }
+                __syncthreads();  // the exchange area becomes the band
+                const int qlo = uniform_i(sh_qmin[cpar]), qhi = uniform_i(sh_qmax[cpar]) + 1;
                 if (qlo > qhi) continue;  // no sample of this cell here (uniform)
                 // rows reaching below this pass: the next tile takes the trace up
                 if (!last_tile && (qhi >> 2) + DD - 1 > out_hi && tid == 0) {
@@ -491,109 +565,112 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 const int rlo = max(qlo, OS * (out_lo - (DD - 1)));
                 const int rhi = min(qhi, OS * out_hi + OS - 1);
                 if (rlo > rhi) continue;
-                for (int A = rlo; A <= rhi; A += NB) {
-                    // 3a. the band: right-slot parts of each column's window in its
-                    // own slot, then (after a barrier) the left-slot parts of
-                    // column c + 1 added into slot c
+                // deposits are non-negative and at most 2 column totals: scale
+                // them into [0, 2^14) for fp16 (an exact power of two)
+                const float dmax = 2.0f * __uint_as_float(uniform_i((int)sh_dmax[cpar]));
+                if (!(dmax > 0.0f)) continue;
+                int dex;
+                frexpf(dmax, &dex);
+                const float dsc = ldexpf(1.0f, 14 - dex);
+                const double unsc = ldexp(1.0, dex - 14 - kTapShift);
+                // this wave's node layer: fragments of its taps (both planes)
+                const int mx = min(nbx + (wv & 1), gxn - 1);
+                const int my = min(nby + (wv >> 1), gyn - 1);
+                gptr<h8> tfr = as_global(reinterpret_cast<const h8 *>(Fp->tfrag)) +
+                               (size_t)(my * gxn + mx) * (2 * 4 * NFR * FRS / 8);
+                for (int A = rlo; A <= rhi; A += 4) {
+                    const int C = A & 3;
+                    // 3a. slot c's deposits in band rows A..A+3, scaled, as fp16
+                    // hi + lo parts
+                    {
+                        const int ro = mrb == kNone ? -8 : A - mrb;  // band row 0 in mw
+                        unsigned short *bs = reinterpret_cast<unsigned short *>(bandbuf);
 #pragma unroll
-                    for (int l = 0; l < 4; ++l)
+                        for (int l = 0; l < 4; ++l) {
+                            u4s hv, lv;
 #pragma unroll
-                        for (int r = 0; r < NB; ++r) band[(l * NB + r) * PR + pc] = 0.0f;
-                    const int ro = rb - A;  // window row 0 in the band
-                    if (rb != kNone) {
+                            for (int r = 0; r < 4; ++r) {
+                                float v = 0.0f;
 #pragma unroll
-                        for (int j = 0; j < 4; ++j)
-                            if ((unsigned)(ro + j) < (unsigned)NB)
+                                for (int u = 0; u < 5; ++u) v = ro + r == u ? mw[l][u] : v;
+                                const float s = v * dsc;
+                                const _Float16 h = (_Float16)s;
+                                const _Float16 lo = (_Float16)(s - (float)h);
+                                hv[r] = __builtin_bit_cast(unsigned short, h);
+                                lv[r] = __builtin_bit_cast(unsigned short, lo);
+                            }
+                            *reinterpret_cast<u4s *>(bs + ((0 * 4 + l) * RL + tid) * 4) = hv;
+                            *reinterpret_cast<u4s *>(bs + ((1 * 4 + l) * RL + tid) * 4) = lv;
+                        }
+                        // slots past the last column read as zeros
+                        if (tid < RL - NCOL) {
+                            const u4s z = {0, 0, 0, 0};
 #pragma unroll
-                                for (int l = 0; l < 4; ++l)
-                                    band[(l * NB + ro + j) * PR + pc] = wr[l][1][j];
+                            for (int pl = 0; pl < 8; ++pl)
+                                *reinterpret_cast<u4s *>(bs + (pl * RL + NCOL + tid) * 4) = z;
+                        }
                     }
                     __syncthreads();
-                    if (rb != kNone && tid > 0) {
+                    // 3c. this wave's layer: out[i][j] for 4 blocks of 16 pixel
+                    // columns.  Lane (lg, l16) reads k = (slot pair 4t + lg, rows
+                    // 0..3): of block row i = l16 from the band (slots 4 i + 2 (4t
+                    // + lg) .. +1), of output row j = l16 from the tap fragments
+                    // of the band phase (loaded one k-step ahead).
+                    f4 acc[4];
+                    {
+                        const int row = min(l16, NJ);
+                        gptr<h8> fh = tfr + ((size_t)(0 * 4 + C) * NFR + row) * (FRS / 8) + lg;
+                        gptr<h8> fl = tfr + ((size_t)(1 * 4 + C) * NFR + row) * (FRS / 8) + lg;
+                        const h8 *bh8 = reinterpret_cast<const h8 *>(bandbuf);
 #pragma unroll
-                        for (int j = 0; j < 4; ++j)
-                            if ((unsigned)(ro + j) < (unsigned)NB)
+                        for (int mb = 0; mb < 4; ++mb) acc[mb] = f4{0.f, 0.f, 0.f, 0.f};
+                        h8 bh = fh[0], bl = fl[0];
 #pragma unroll
-                                for (int l = 0; l < 4; ++l)
-                                    band[(l * NB + ro + j) * PR + pcl] += wr[l][0][j];
-                    }
-                    __syncthreads();
-
-                    // 3b. stencil: wave wv takes slot offsets s = wv*SQ .. +SQ-1 of
-                    // every node layer; lane = pixel column.  Band row r has
-                    // phase (A + r) & 3 and output offset ((A & 3) + r) >> 2; the
-                    // code is specialised on A & 3 so both are compile-time.
-                    double acc[NJ];
-#pragma unroll
-                    for (int d = 0; d < NJ; ++d) acc[d] = 0.0;
-                    const int s0 = wv * SQ;
-                    cptr<float> tbase = as_const(Fp->tb) + (size_t)s0 * OS * DD;
-                    auto stencil = [&](auto cph) {
-                        constexpr int C = decltype(cph)::value;
-#pragma unroll 1
-                        for (int L = 0; L < 4; ++L) {
-                            const int mx = min(nbx + (L & 1), gxn - 1);
-                            const int my = min(nby + (L >> 1), gyn - 1);
-                            cptr<float> taps = tbase + (size_t)(my * gxn + mx) * NODE;
-                            float a32[NJ];
-#pragma unroll
-                            for (int d = 0; d < NJ; ++d) a32[d] = 0.0f;
-#pragma unroll 1
-                            for (int ss = 0; ss < SQ; ++ss) {
-                                const int sl = s0 + ss;
-                                if (sl >= NS) break;  // uniform
-                                const int a = (sl & 3) * PQ + clane + (sl >> 2);
-                                float dv[NB];
-                                float tv[NB][DD];
-#pragma unroll
-                                for (int r = 0; r < NB; ++r) {
-                                    dv[r] = band[(L * NB + r) * PR + a];
-                                    const int p = (C + r) & 3;
-#pragma unroll
-                                    for (int dd = 0; dd < DD; ++dd)
-                                        tv[r][dd] = taps[(ss * OS + p) * DD + dd];
-                                }
-#pragma unroll
-                                for (int r = 0; r < NB; ++r) {
-                                    const int p = (C + r) & 3, n = (C + r) >> 2;
-#pragma unroll
-                                    for (int dd = 0; dd < DD; ++dd) {
-                                        if (p == 0 && dd == DD - 1) continue;  // zero tap row
-                                        a32[n + dd] = fmaf(dv[r], tv[r][dd], a32[n + dd]);
-                                    }
-                                }
+                        for (int t = 0; t < NKS; ++t) {
+                            h8 nh = bh, nl = bl;
+                            if (t + 1 < NKS) {
+                                nh = fh[4 * (t + 1)];
+                                nl = fl[4 * (t + 1)];
                             }
 #pragma unroll
-                            for (int d = 0; d < NJ; ++d) acc[d] += (double)a32[d];
-                        }
-                    };
-                    switch (A & 3) {
-                    case 0: stencil(std::integral_constant<int, 0>()); break;
-                    case 1: stencil(std::integral_constant<int, 1>()); break;
-                    case 2: stencil(std::integral_constant<int, 2>()); break;
-                    default: stencil(std::integral_constant<int, 3>()); break;
-                    }
-                    // 3c. fixed-order sum of the four partials into the tile
-                    __syncthreads();
-                    double *P = bandbuf;
-                    if (wv > 0) {
-#pragma unroll
-                        for (int d = 0; d < NJ; ++d) P[((wv - 1) * NJ + d) * 64 + lane] = acc[d];
-                    }
-                    __syncthreads();
-                    if (wv == 0 && lane < TW) {
-#pragma unroll
-                        for (int d = 0; d < NJ; ++d) {
-                            const int o = (A >> 2) + d;  // output row
-                            if (o < out_lo || o > out_hi) continue;
-                            const double v = ((acc[d] + P[d * 64 + lane]) +
-                                              P[(NJ + d) * 64 + lane]) +
-                                             P[(2 * NJ + d) * 64 + lane];
-                            if (o < Y0 + TH) tile[o - Y0][lane] += v;
-                            else carry[o - Y0 - TH][lane] += v;
+                            for (int mb = 0; mb < 4; ++mb) {
+                                const int slot = 4 * (16 * mb + l16) + 2 * (4 * t + lg);
+                                const h8 ah = bh8[((0 * 4 + wv) * RL + slot) / 2];
+                                const h8 al = bh8[((1 * 4 + wv) * RL + slot) / 2];
+                                acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, acc[mb], 0, 0, 0);
+                                acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, acc[mb], 0, 0, 0);
+                                acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, acc[mb], 0, 0, 0);
+                            }
+                            bh = nh;
+                            bl = nl;
                         }
                     }
                     __syncthreads();
+                    // 3d. the layer partials, then a fixed-order FP64 sum per
+                    // pixel into the tile (wave w adds column block w)
+                    f4 *part = reinterpret_cast<f4 *>(bandbuf);
+#pragma unroll
+                    for (int mb = 0; mb < 4; ++mb) part[(wv * 4 + mb) * 64 + lane] = acc[mb];
+                    __syncthreads();
+                    {
+                        const f4 p0 = part[(0 * 4 + wv) * 64 + lane];
+                        const f4 p1 = part[(1 * 4 + wv) * 64 + lane];
+                        const f4 p2 = part[(2 * 4 + wv) * 64 + lane];
+                        const f4 p3 = part[(3 * 4 + wv) * 64 + lane];
+                        const int o = (A >> 2) + l16;  // output row
+                        if (l16 < NJ && o >= out_lo && o <= out_hi) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const int i = 16 * wv + 4 * lg + e;  // pixel column
+                                if (i < TW) {
+                                    const double v = ((((double)p0[e] + (double)p1[e]) +
+                                                       (double)p2[e]) + (double)p3[e]) * unsc;
+                                    if (o < Y0 + TH) tile[o - Y0][i] += v;
+                                    else carry[o - Y0 - TH][i] += v;
+                                }
+                            }
+                        }
+                    }
                 }
             }
         }

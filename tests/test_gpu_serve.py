@@ -114,7 +114,11 @@ def test_serve_admission_by_footprint():
     gu = _gu()
     sc = scene("mini_table")
     ntx = -(-sc.nx // 56)
-    tables = sc.psf.gx * sc.psf.gy * 4 * 35 * 9 * 4 + len(sc.traces) * 176  # FP32 taps
+    # resident tables: per node the fp16 hi/lo tap fragments, [2][4 phases]
+    # [dd + 2 rows][padded slot offsets][4 band rows]; per trace its record
+    dd = (sc.psf.kw + 2) // 4 + 1
+    sp = (sc.psf.kw + 3 + 7) // 8 * 8
+    tables = sc.psf.gx * sc.psf.gy * 2 * 4 * (dd + 2) * sp * 4 * 2 + len(sc.traces) * 176
     footprint = sc.nx * sc.ny * 4 + ntx * len(sc.traces) * 16
     ctx = E.e2e_create(0, tables + int(1.5 * footprint))
     ld = P.Loaded(ctx, sc)
