@@ -42,6 +42,19 @@ namespace {
 constexpr int kNone = 0x3fffffff;  // "no row yet"; far from any real row
 constexpr int kUnf = 64;           // traces one tile can hand on to the next
 
+// k! S(i, k), S the Stirling numbers of the second kind: the k-th forward
+// difference at 0 of j^i (unit step), for i, k <= 7
+__device__ constexpr double kFwd[8][8] = {
+    {1, 0, 0, 0, 0, 0, 0, 0},
+    {0, 1, 0, 0, 0, 0, 0, 0},
+    {0, 1, 2, 0, 0, 0, 0, 0},
+    {0, 1, 6, 6, 0, 0, 0, 0},
+    {0, 1, 14, 36, 24, 0, 0, 0},
+    {0, 1, 30, 150, 240, 120, 0, 0},
+    {0, 1, 62, 540, 1560, 1800, 720, 0},
+    {0, 1, 126, 1806, 8400, 16800, 15120, 5040},
+};
+
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u4s __attribute__((ext_vector_type(4)));
@@ -385,6 +398,9 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 bool run_in = false;
                 int qmin = 0x7fffffff, qmax = -0x7fffffff;
                 double csum = 0.0;  // photons of the column (bounds its deposits)
+                // the x factor (CIC x node weight) of each deposit is a0 + a1 rx +
+                // a2 rx^2 with these coefficients, times the flux scale
+                const double xs = scale, xa = fxa * scale, xb = fxb * scale;
 
                 auto flush = [&]() {
                     const int o = runQy - rb;
@@ -398,16 +414,18 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                     }
                     csum += m[0][0];
                     const double fya = fma(ay1, ((double)runQy - UC) / OS, ay0);
-                    // polynomial coefficients (in rho) of cic x node weight
-                    double X[2][2][3], Y[2][2][3];
-                    auto coef = [](double a, double b, double c[2][2][3]) {
-                        c[0][1][0] = a;       c[0][1][1] = b - a;       c[0][1][2] = -b;
-                        c[0][0][0] = 1.0 - a; c[0][0][1] = a - 1.0 - b; c[0][0][2] = b;
-                        c[1][1][0] = 0.0;     c[1][1][1] = a;           c[1][1][2] = b;
-                        c[1][0][0] = 0.0;     c[1][0][1] = 1.0 - a;     c[1][0][2] = -b;
-                    };
-                    coef(fxa, fxb, X);
-                    coef(fya, fyb, Y);
+                    // y factor (CIC x node weight) of row half r, node ny:
+                    // Y[r][ny][0] + Y[r][ny][1] ry + Y[r][ny][2] ry^2
+                    double Y[2][2][3];
+                    Y[0][1][0] = fya;       Y[0][1][1] = fyb - fya;       Y[0][1][2] = -fyb;
+                    Y[0][0][0] = 1.0 - fya; Y[0][0][1] = fya - 1.0 - fyb; Y[0][0][2] = fyb;
+                    Y[1][1][0] = 0.0;       Y[1][1][1] = fya;             Y[1][1][2] = fyb;
+                    Y[1][0][0] = 0.0;       Y[1][0][1] = 1.0 - fya;       Y[1][0][2] = -fyb;
+                    double X[2][2][3];
+                    X[0][1][0] = xa;      X[0][1][1] = xb - xa;      X[0][1][2] = -xb;
+                    X[0][0][0] = xs - xa; X[0][0][1] = xa - xs - xb; X[0][0][2] = xb;
+                    X[1][1][0] = 0.0;     X[1][1][1] = xa;           X[1][1][2] = xb;
+                    X[1][0][0] = 0.0;     X[1][0][1] = xs - xa;      X[1][0][2] = -xb;
                     double Tm[2][2][3];
 #pragma unroll
                     for (int r = 0; r < 2; ++r)
@@ -417,51 +435,115 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                             for (int a = 0; a < 3; ++a)
                                 Tm[r][ny][a] = fma(Y[r][ny][2], m[a][2],
                                                    fma(Y[r][ny][1], m[a][1], Y[r][ny][0] * m[a][0]));
+                    float dv[4][2][2];
 #pragma unroll
                     for (int l = 0; l < 4; ++l)
 #pragma unroll
-                        for (int lr = 0; lr < 2; ++lr) {
-                            const int nx = l & 1, ny = l >> 1;
-                            float dv[2];
+                        for (int lr = 0; lr < 2; ++lr)
 #pragma unroll
                             for (int r = 0; r < 2; ++r) {
-                                double d = fma(X[lr][nx][2], Tm[r][ny][2],
-                                               fma(X[lr][nx][1], Tm[r][ny][1],
-                                                   X[lr][nx][0] * Tm[r][ny][0]));
-                                dv[r] = (float)(d * scale);
+                                const int nx = l & 1, ny = l >> 1;
+                                dv[l][lr][r] = (float)fma(X[lr][nx][2], Tm[r][ny][2],
+                                                          fma(X[lr][nx][1], Tm[r][ny][1],
+                                                              X[lr][nx][0] * Tm[r][ny][0]));
                             }
-                            wr[l][lr][0] += o == 0 ? dv[0] : 0.0f;
-                            wr[l][lr][1] += o == 0 ? dv[1] : (o == 1 ? dv[0] : 0.0f);
-                            wr[l][lr][2] += o == 1 ? dv[1] : (o == 2 ? dv[0] : 0.0f);
-                            wr[l][lr][3] += o == 2 ? dv[1] : 0.0f;
-                        }
+                    // rows runQy, runQy + 1 are window rows o, o + 1: fixed rows 1, 2
+                    // for a column's first run (the usual case), selects otherwise
+                    // (a dynamic index would move the window out of registers)
+                    if (o == 1) {
+#pragma unroll
+                        for (int l = 0; l < 4; ++l)
+#pragma unroll
+                            for (int lr = 0; lr < 2; ++lr) {
+                                wr[l][lr][1] += dv[l][lr][0];
+                                wr[l][lr][2] += dv[l][lr][1];
+                            }
+                    } else {
+                        const bool o0 = o == 0, o2 = o == 2;
+#pragma unroll
+                        for (int l = 0; l < 4; ++l)
+#pragma unroll
+                            for (int lr = 0; lr < 2; ++lr) {
+                                const float d0 = dv[l][lr][0], d1 = dv[l][lr][1];
+                                wr[l][lr][0] += o0 ? d0 : 0.0f;
+                                wr[l][lr][1] += o0 ? d1 : 0.0f;
+                                wr[l][lr][2] += o2 ? d0 : 0.0f;
+                                wr[l][lr][3] += o2 ? d1 : 0.0f;
+                            }
+                    }
                 };
-                const double UCq = UC - (double)q;
-                auto sample = [&](int k, double sv, auto mc) {
-                    double t = fma((double)k, dt, t0);
-                    double x = horner<DX>(cxr, t);
-                    double y = horner<DY>(cyr, t);
-                    double rx = fma(x, (double)OS, UCq);
-                    double vy = fma(y, (double)OS, UC);
-                    double fly = floor(vy);
-                    int Qy = (int)fly;
-                    double ry = vy - fly;
-                    bool in = true;
-                    if constexpr (decltype(mc)::value)
-                        in = (ext_cell(x, gsx, gxn) == cxc) & (ext_cell(y, gsy, gyn) == cyc);
-                    double phi = in ? sv : 0.0;
-                    if (Qy != runQy) {
-                        if (runQy != kNone) {
-                            flush();
+                // Positions of the column's samples ks + j by forward differences
+                // of the FP64 format polynomials (exact up to rounding): px is
+                // u - q = OS x + UC - q (the slot phase rx), py is OS y + UC - runQy
+                // (the row phase ry of the current run).
+                double px[DX + 1], py[DY + 1];
+                auto setup = [&]() {
+                    const double ts = fma((double)ks, dt, t0);
+                    // Taylor coefficients at ts (synthetic division), in powers of
+                    // j dt, scaled to slots
+                    double bx[DX + 1], by[DY + 1];
 #pragma unroll
-                            for (int a = 0; a < 3; ++a)
+                    for (int i = 0; i <= DX; ++i) bx[i] = cxr[i];
 #pragma unroll
-                                for (int b = 0; b < 3; ++b) m[a][b] = 0.0;
-                        }
-                        if (rb == kNone) rb = Qy - 1;
-                        runQy = Qy;
+                    for (int i = 0; i <= DY; ++i) by[i] = cyr[i];
+#pragma unroll
+                    for (int i = 0; i < DX; ++i)
+#pragma unroll
+                        for (int k = DX - 1; k >= i; --k) bx[k] = fma(ts, bx[k + 1], bx[k]);
+#pragma unroll
+                    for (int i = 0; i < DY; ++i)
+#pragma unroll
+                        for (int k = DY - 1; k >= i; --k) by[k] = fma(ts, by[k + 1], by[k]);
+                    double h = (double)OS;
+#pragma unroll
+                    for (int i = 0; i <= (DX > DY ? DX : DY); ++i) {
+                        if (i <= DX) bx[i] *= h;
+                        if (i <= DY) by[i] *= h;
+                        h *= dt;
+                    }
+                    // forward differences at j = 0: d^k P = sum_i p_i k! S(i, k)
+#pragma unroll
+                    for (int k = 1; k <= DX; ++k) {
+                        double d = 0.0;
+#pragma unroll
+                        for (int i = DX; i >= k; --i) d = fma(bx[i], kFwd[i][k], d);
+                        px[k] = d;
+                    }
+#pragma unroll
+                    for (int k = 1; k <= DY; ++k) {
+                        double d = 0.0;
+#pragma unroll
+                        for (int i = DY; i >= k; --i) d = fma(by[i], kFwd[i][k], d);
+                        py[k] = d;
+                    }
+                    px[0] = bx[0] + (UC - (double)q);
+                    const double vy = by[0] + UC, fl = floor(vy);
+                    runQy = (int)fl;
+                    rb = runQy - 1;
+                    py[0] = vy - fl;
+                };
+                auto sample = [&](double sv, auto mc) {
+                    double rx = px[0];
+                    double ry = py[0];
+                    if (ry < 0.0 || ry >= 1.0) {  // the row changes (rare)
+                        flush();
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+#pragma unroll
+                            for (int b = 0; b < 3; ++b) m[a][b] = 0.0;
+                        const double f = floor(ry);
+                        runQy += (int)f;
+                        ry -= f;
+                        py[0] = ry;
                         run_in = false;
                     }
+                    bool in = true;
+                    if constexpr (decltype(mc)::value) {
+                        const double x = (rx + ((double)q - UC)) / OS;
+                        const double y = (ry + ((double)runQy - UC)) / OS;
+                        in = (ext_cell(x, gsx, gxn) == cxc) & (ext_cell(y, gsy, gyn) == cyc);
+                    }
+                    const double phi = in ? sv : 0.0;
                     run_in |= in;
                     const double e1 = phi * ry, e2 = e1 * ry, rx2 = rx * rx;
                     m[0][0] += phi;
@@ -473,11 +555,17 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                     m[2][0] = fma(phi, rx2, m[2][0]);
                     m[2][1] = fma(e1, rx2, m[2][1]);
                     m[2][2] = fma(e2, rx2, m[2][2]);
+                    // next sample
+#pragma unroll
+                    for (int k = 0; k < DX; ++k) px[k] += px[k + 1];
+#pragma unroll
+                    for (int k = 0; k < DY; ++k) py[k] += py[k + 1];
                 };
                 // a trace segment that stays in one node cell (the usual case)
                 // needs no per-sample cell test: two instances of the loop
                 auto walk = [&](auto mc) {
                     if (ks >= ke) return;
+                    setup();
                     // spectrum values G at a time (one 16-byte load per lane),
                     // the next group's load issued before this group's samples
                     constexpr int G = SpecVec<ST>::G;
@@ -487,7 +575,7 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                         SpecVec<ST>::load(spec, min(kb + G, ke - 1), nspec, nv);
 #pragma unroll
                         for (int e = 0; e < G; ++e)
-                            if (kb + e < ke) sample(kb + e, (double)v[e], mc);
+                            if (kb + e < ke) sample((double)v[e], mc);
 #pragma unroll
                         for (int e = 0; e < G; ++e) v[e] = nv[e];
                     }
@@ -522,36 +610,6 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 // ---- 3. stencils over bands of 4 consecutive deposit rows (any
                 // start).  Deposit row 4n + p reaches output rows n .. n + DD - 1;
                 // a band starting at A spans output rows A/4 .. A/4 + NJ - 1.
-                // slot c's deposits: its right-slot halves and column c + 1's
-                // left-slot halves.  Adjacent columns' first rows differ by at
-                // most one (|dy/dx| <= 1/2 over a quarter pixel), so slot c's
-                // rows fit a 5-row window from mrb.
-                float mw[4][5];
-                int mrb;
-                {
-                    const int nrb = tid + 1 < NCOL ? __float_as_int(xw[(tid + 1) * XS + 16]) : kNone;
-                    mrb = rb == kNone ? nrb : (nrb == kNone ? rb : min(rb, nrb));
-                    const int da = rb == kNone ? 8 : rb - mrb, dn = nrb == kNone ? 8 : nrb - mrb;
-                    if (da > 1 && da != 8) atomicOr(err, kErrRowWindow);
-                    if (dn > 1 && dn != 8) atomicOr(err, kErrRowWindow);
-#pragma unroll
-                    for (int l = 0; l < 4; ++l) {
-                        float nl[4];
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            nl[r] = tid + 1 < NCOL ? xw[(tid + 1) * XS + l * 4 + r] : 0.0f;
-#pragma unroll
-                        for (int u = 0; u < 5; ++u) {
-                            float a = 0.0f, b = 0.0f;
-                            if (u < 4) a = da == 0 ? wr[l][1][u] : a;
-                            if (u >= 1) a = da == 1 ? wr[l][1][u - 1] : a;
-                            if (u < 4) b = dn == 0 ? nl[u] : b;
-                            if (u >= 1) b = dn == 1 ? nl[u - 1] : b;
-                            mw[l][u] = a + b;
-                        }
-                    }
-                }
-                __syncthreads();  // the exchange area becomes the band
                 const int qlo = uniform_i(sh_qmin[cpar]), qhi = uniform_i(sh_qmax[cpar]) + 1;
                 if (qlo > qhi) continue;  // no sample of this cell here (uniform)
                 // rows reaching below this pass: the next tile takes the trace up
@@ -573,6 +631,58 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 frexpf(dmax, &dex);
                 const float dsc = ldexpf(1.0f, 14 - dex);
                 const double unsc = ldexp(1.0, dex - 14 - kTapShift);
+                // slot c's deposits: its right-slot halves and column c + 1's
+                // left-slot halves.  Adjacent columns' first rows differ by at
+                // most one (|dy/dx| <= 1/2 over a quarter pixel), so slot c's
+                // rows fit a 5-row window from mrb.  Each layer's window is kept
+                // scaled, as fp16 hi and lo parts packed four rows to a 64-bit
+                // word: rows 1..4 in w1[l], row 0 in the top half of w0[l].
+                unsigned long long w1h[4], w1l[4];
+                unsigned w0h[4], w0l[4];
+                int mrb;
+                {
+                    const int nrb = tid + 1 < NCOL ? __float_as_int(xw[(tid + 1) * XS + 16]) : kNone;
+                    mrb = rb == kNone ? nrb : (nrb == kNone ? rb : min(rb, nrb));
+                    const int da = rb == kNone ? 8 : rb - mrb, dn = nrb == kNone ? 8 : nrb - mrb;
+                    if (da > 1 && da != 8) atomicOr(err, kErrRowWindow);
+                    if (dn > 1 && dn != 8) atomicOr(err, kErrRowWindow);
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        float nl[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            nl[r] = tid + 1 < NCOL ? xw[(tid + 1) * XS + l * 4 + r] : 0.0f;
+                        unsigned hh[5], ll[5];
+#pragma unroll
+                        for (int u = 0; u < 5; ++u) {
+                            float a = 0.0f, b = 0.0f;
+                            if (u < 4) a = da == 0 ? wr[l][1][u] : a;
+                            if (u >= 1) a = da == 1 ? wr[l][1][u - 1] : a;
+                            if (u < 4) b = dn == 0 ? nl[u] : b;
+                            if (u >= 1) b = dn == 1 ? nl[u - 1] : b;
+                            const float v = (a + b) * dsc;
+                            const _Float16 h = (_Float16)v;
+                            const _Float16 lo = (_Float16)(v - (float)h);
+                            hh[u] = __builtin_bit_cast(unsigned short, h);
+                            ll[u] = __builtin_bit_cast(unsigned short, lo);
+                        }
+                        w0h[l] = hh[0] << 16;
+                        w0l[l] = ll[0] << 16;
+                        w1h[l] = (unsigned long long)(hh[1] | (hh[2] << 16)) |
+                                 ((unsigned long long)(hh[3] | (hh[4] << 16)) << 32);
+                        w1l[l] = (unsigned long long)(ll[1] | (ll[2] << 16)) |
+                                 ((unsigned long long)(ll[3] | (ll[4] << 16)) << 32);
+                    }
+                }
+                __syncthreads();  // the exchange area becomes the band
+                // rows A - mrb .. A - mrb + 3 of the packed window (zero outside):
+                // with o = A - mrb + 3, halfs o..o+3 of [0, 0, 0, row 0 .. row 4, 0 ...]
+                auto band4 = [](unsigned w0, unsigned long long w1, int o) -> unsigned long long {
+                    if (o < 0 || o > 7) return 0ull;
+                    if (o >= 4) return w1 >> (16 * (o - 4));
+                    const unsigned long long w0x = (unsigned long long)w0 << 32;
+                    return o == 0 ? w0x : (w0x >> (16 * o)) | (w1 << (64 - 16 * o));
+                };
                 // this wave's node layer: fragments of its taps (both planes)
                 const int mx = min(nbx + (wv & 1), gxn - 1);
                 const int my = min(nby + (wv >> 1), gyn - 1);
@@ -583,24 +693,14 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                     // 3a. slot c's deposits in band rows A..A+3, scaled, as fp16
                     // hi + lo parts
                     {
-                        const int ro = mrb == kNone ? -8 : A - mrb;  // band row 0 in mw
+                        const int o = mrb == kNone ? -8 : A - mrb + 3;
                         unsigned short *bs = reinterpret_cast<unsigned short *>(bandbuf);
 #pragma unroll
                         for (int l = 0; l < 4; ++l) {
-                            u4s hv, lv;
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                float v = 0.0f;
-#pragma unroll
-                                for (int u = 0; u < 5; ++u) v = ro + r == u ? mw[l][u] : v;
-                                const float s = v * dsc;
-                                const _Float16 h = (_Float16)s;
-                                const _Float16 lo = (_Float16)(s - (float)h);
-                                hv[r] = __builtin_bit_cast(unsigned short, h);
-                                lv[r] = __builtin_bit_cast(unsigned short, lo);
-                            }
-                            *reinterpret_cast<u4s *>(bs + ((0 * 4 + l) * RL + tid) * 4) = hv;
-                            *reinterpret_cast<u4s *>(bs + ((1 * 4 + l) * RL + tid) * 4) = lv;
+                            *reinterpret_cast<unsigned long long *>(bs + ((0 * 4 + l) * RL + tid) * 4) =
+                                band4(w0h[l], w1h[l], o);
+                            *reinterpret_cast<unsigned long long *>(bs + ((1 * 4 + l) * RL + tid) * 4) =
+                                band4(w0l[l], w1l[l], o);
                         }
                         // slots past the last column read as zeros
                         if (tid < RL - NCOL) {
@@ -621,7 +721,9 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                         const int row = min(l16, NJ);
                         gptr<h8> fh = tfr + ((size_t)(0 * 4 + C) * NFR + row) * (FRS / 8) + lg;
                         gptr<h8> fl = tfr + ((size_t)(1 * 4 + C) * NFR + row) * (FRS / 8) + lg;
-                        const h8 *bh8 = reinterpret_cast<const h8 *>(bandbuf);
+                        // this lane's band row: slot 4 l16 + 2 lg of layer wv, plane 0
+                        const h8 *ap = reinterpret_cast<const h8 *>(bandbuf) +
+                                       ((wv * RL + 4 * l16 + 2 * lg) >> 1);
 #pragma unroll
                         for (int mb = 0; mb < 4; ++mb) acc[mb] = f4{0.f, 0.f, 0.f, 0.f};
                         h8 bh = fh[0], bl = fl[0];
@@ -634,9 +736,9 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                             }
 #pragma unroll
                             for (int mb = 0; mb < 4; ++mb) {
-                                const int slot = 4 * (16 * mb + l16) + 2 * (4 * t + lg);
-                                const h8 ah = bh8[((0 * 4 + wv) * RL + slot) / 2];
-                                const h8 al = bh8[((1 * 4 + wv) * RL + slot) / 2];
+                                // slots 64 mb + 8 t further on; plane 1 is 4 rows of RL later
+                                const h8 ah = ap[32 * mb + 4 * t];
+                                const h8 al = ap[32 * mb + 4 * t + 2 * RL];
                                 acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, acc[mb], 0, 0, 0);
                                 acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, acc[mb], 0, 0, 0);
                                 acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, acc[mb], 0, 0, 0);
