@@ -212,6 +212,23 @@ e2e_status e2e_psf_free(e2e_ctx *ctx, e2e_psf_id id);
  */
 e2e_status e2e_render(e2e_ctx *ctx, const e2e_render_req *req);
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): e2e_render
+ * of one frame whose spectra and output are on the device, with every buffer
+ * the render needs beyond the caller's inputs and output (planner output,
+ * frame record, spectrum pointers, error word, work counter) taken from a
+ * fixed 16 MiB device array that each GPU holds until the process ends; the
+ * call makes no hipMalloc, hipHostMalloc or hipFree.  Synchronous (returns
+ * when the frame is written); E2E_FLAG_ASYNC is ignored.  Limits: at most 64
+ * spectrum slots, and planner output of at most about 16 MiB
+ * (16 B x tile columns x traces + 32 B x traces), else E2E_ENOMEM with the
+ * size in the message; host spectra or output, E2E_EINVAL.  The array is
+ * shared by every call on that GPU and keeps the last call's contents: calls
+ * that overlap on one GPU (several threads, several contexts) race and must
+ * be serialised by the caller.  Results equal e2e_render's bit for bit.
+ */
+e2e_status e2e_render_noalloc(e2e_ctx *ctx, const e2e_render_req *req);
+/*
  * Render n frames of any sizes / formats sharing one PSF kind in one
  * persistent launch that pulls (frame, tile) work items from a queue;
  * results are bitwise identical to e2e_render of each frame.

@@ -44,6 +44,11 @@ double e2e::now_us(const e2e_ctx *ctx)
 
 // ------------------------------------------------------------------ context
 
+// The allocation-free render's device memory (e2e_render_noalloc): each
+// device holds its own copy for the life of the process.  Host code must use
+// the address hipGetSymbolAddress returns on that device, never this name.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 extern "C" e2e_status e2e_create(e2e_ctx **out, int32_t dev, uint64_t budget)
 {
     if (!out) return fail(E2E_EINVAL, "e2e_create: out is NULL");
@@ -65,6 +70,12 @@ extern "C" e2e_status e2e_create(e2e_ctx **out, int32_t dev, uint64_t budget)
     if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
         delete c;
         return hip_fail(e, "hipStreamCreate");
+    }
+    // this device's copy of the allocation-free render's array (dev is current)
+    if ((e = hipGetSymbolAddress((void **)&c->noalloc.base, HIP_SYMBOL(scratch))) != hipSuccess) {
+        hipStreamDestroy(c->stream);
+        delete c;
+        return hip_fail(e, "hipGetSymbolAddress(scratch)");
     }
     *out = c;
     return E2E_OK;
@@ -575,11 +586,12 @@ static void tile_geom(const PsfRes *P, int precision, int *tw, int *th)
 }
 
 e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool batch,
-                           int *batch_sizes_out)
+                           bool noalloc)
 {
-    (void)batch_sizes_out;
     if (!ctx) return fail(E2E_EINVAL, "NULL context");
     if (n < 1) return fail(E2E_EINVAL, "n=%d", n);
+    if (noalloc && (n != 1 || batch || !reqs[0].out_on_device || !reqs[0].spectra_on_device))
+        return fail(E2E_EINVAL, "e2e_render_noalloc: one frame, device spectra and output");
     hipSetDevice(ctx->dev);
     std::lock_guard<std::mutex> lk(ctx->mu);
     std::vector<FormatRes *> fs(n);
@@ -599,8 +611,16 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
             return fail(E2E_EINVAL, "batch frames must share one stream");
     }
     hipStream_t s = reqs[0].hip_stream ? (hipStream_t)reqs[0].hip_stream : ctx->stream;
-    Scratch *sc = scratch_for(ctx, s);
+    // the allocation-free render uses a Scratch view of the device array
+    Scratch na_sc;
+    Scratch *sc = noalloc ? &na_sc : scratch_for(ctx, s);
     if (!sc) return fail(E2E_EDEVICE, "scratch allocation failed");
+    if (noalloc) {
+        if (!ctx->noalloc.base) return fail(E2E_EDEVICE, "no allocation-free scratch on device");
+        sc->err = reinterpret_cast<int *>(ctx->noalloc.base);
+        sc->counter = reinterpret_cast<int *>(ctx->noalloc.base + 64);
+        sc->err_host = &ctx->noalloc.err_host;
+    }
     // temporaries of the previous call on this stream are free once the
     // stream has passed it
     hipError_t e = hipSuccess;
@@ -658,18 +678,36 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
         return fail(E2E_ENOMEM, "render needs %zu bytes beyond the %llu-byte budget",
                     temp_bytes + scratch_need, (unsigned long long)ctx->budget);
     e2e_status st;
+    if (noalloc) {
+        // [err, counter | frame record | spectrum pointers | planner output]
+        auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+        const size_t o_fr = 256, o_sp = o_fr + up(sizeof(FrameDev));
+        const size_t o_seg = o_sp + up(kParamSlots * sizeof(void *));
+        if (nslots_total > kParamSlots)
+            return fail(E2E_EINVAL, "e2e_render_noalloc: %d spectrum slots, at most %d",
+                        nslots_total, kParamSlots);
+        if (o_seg + seg_bytes + 16 > kNoAllocBytes)
+            return fail(E2E_ENOMEM,
+                        "e2e_render_noalloc: needs %zu bytes of scratch, the limit is %zu",
+                        o_seg + seg_bytes + 16, kNoAllocBytes);
+        sc->frames_dev = reinterpret_cast<FrameDev *>(ctx->noalloc.base + o_fr);
+        sc->specptrs = reinterpret_cast<const void **>(ctx->noalloc.base + o_sp);
+        sc->segs = reinterpret_cast<SegDev *>(ctx->noalloc.base + o_seg);
+    }
     // planner output: segments of every frame, then the per-trace constants
-    if ((st = grow((void **)&sc->segs, &sc->segs_cap, seg_bytes + 16, "segs")) != E2E_OK)
+    if (!noalloc && (st = grow((void **)&sc->segs, &sc->segs_cap, seg_bytes + 16, "segs")) != E2E_OK)
         return st;
-    if ((st = grow((void **)&sc->frames_dev, &sc->frames_cap, n * sizeof(FrameDev),
-                   "frames")) != E2E_OK)
-        return st;
-    if ((st = grow((void **)&sc->work, &sc->work_cap, work_n * sizeof(int2) + 16, "work")) !=
-        E2E_OK)
-        return st;
-    if ((st = grow((void **)&sc->specptrs, &sc->specptrs_cap,
-                   nslots_total * sizeof(void *) + 16, "spectra")) != E2E_OK)
-        return st;
+    if (!noalloc) {
+        if ((st = grow((void **)&sc->frames_dev, &sc->frames_cap, n * sizeof(FrameDev),
+                       "frames")) != E2E_OK)
+            return st;
+        if ((st = grow((void **)&sc->work, &sc->work_cap, work_n * sizeof(int2) + 16, "work")) !=
+            E2E_OK)
+            return st;
+        if ((st = grow((void **)&sc->specptrs, &sc->specptrs_cap,
+                       nslots_total * sizeof(void *) + 16, "spectra")) != E2E_OK)
+            return st;
+    }
 
     // spectra pointers (device), host spectra copied to temporaries
     sc->h_specptrs.assign(nslots_total, nullptr);
@@ -756,37 +794,47 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
         for (int i : order)
             for (int t = 0; t < tiles[i]; ++t) sc->h_work.push_back(make_int2(i, t));
     }
-    // parameter upload through pinned staging (reused once its copy ran)
-    size_t b_spec = nslots_total * sizeof(void *), b_fr = n * sizeof(FrameDev),
-           b_work = batch ? work_n * sizeof(int2) : 0;
-    size_t b_all = b_spec + b_fr + b_work + 64;
-    if (sc->staged_valid) {
-        if ((e = hipEventSynchronize(sc->staged)) != hipSuccess) return hip_fail(e, "staging");
+    if (noalloc) {
+        // parameters travel as a kernel argument: no staging buffer
+        FrameParams prm{};
+        prm.f = sc->h_frames[0];
+        prm.nslots = nslots_total;
+        for (int q = 0; q < nslots_total; ++q) prm.spec[q] = sc->h_specptrs[q];
+        if ((e = launch_put_params(prm, sc->frames_dev, sc->specptrs, s)) != hipSuccess)
+            return hip_fail(e, "parameter kernel");
+    } else {
+        // parameter upload through pinned staging (reused once its copy ran)
+        size_t b_spec = nslots_total * sizeof(void *), b_fr = n * sizeof(FrameDev),
+               b_work = batch ? work_n * sizeof(int2) : 0;
+        size_t b_all = b_spec + b_fr + b_work + 64;
+        if (sc->staged_valid) {
+            if ((e = hipEventSynchronize(sc->staged)) != hipSuccess) return hip_fail(e, "staging");
+        }
+        if (sc->stage_cap < b_all) {
+            if (sc->stage) hipHostFree(sc->stage);
+            sc->stage = nullptr;
+            sc->stage_cap = 0;
+            if ((e = hipHostMalloc(&sc->stage, b_all * 2)) != hipSuccess) return hip_fail(e, "staging");
+            sc->stage_cap = b_all * 2;
+        }
+        if (!sc->staged) {
+            if ((e = hipEventCreateWithFlags(&sc->staged, hipEventDisableTiming)) != hipSuccess)
+                return hip_fail(e, "event");
+        }
+        char *stg = (char *)sc->stage;
+        memcpy(stg, sc->h_specptrs.data(), b_spec);
+        memcpy(stg + b_spec, sc->h_frames.data(), b_fr);
+        if (b_work) memcpy(stg + b_spec + b_fr, sc->h_work.data(), b_work);
+        if ((e = hipMemcpyAsync(sc->specptrs, stg, b_spec, hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(sc->frames_dev, stg + b_spec, b_fr, hipMemcpyHostToDevice, s)) !=
+                hipSuccess)
+            return hip_fail(e, "parameter upload");
+        if (b_work && (e = hipMemcpyAsync(sc->work, stg + b_spec + b_fr, b_work,
+                                          hipMemcpyHostToDevice, s)) != hipSuccess)
+            return hip_fail(e, "work upload");
+        if ((e = hipEventRecord(sc->staged, s)) != hipSuccess) return hip_fail(e, "event");
+        sc->staged_valid = true;
     }
-    if (sc->stage_cap < b_all) {
-        if (sc->stage) hipHostFree(sc->stage);
-        sc->stage = nullptr;
-        sc->stage_cap = 0;
-        if ((e = hipHostMalloc(&sc->stage, b_all * 2)) != hipSuccess) return hip_fail(e, "staging");
-        sc->stage_cap = b_all * 2;
-    }
-    if (!sc->staged) {
-        if ((e = hipEventCreateWithFlags(&sc->staged, hipEventDisableTiming)) != hipSuccess)
-            return hip_fail(e, "event");
-    }
-    char *stg = (char *)sc->stage;
-    memcpy(stg, sc->h_specptrs.data(), b_spec);
-    memcpy(stg + b_spec, sc->h_frames.data(), b_fr);
-    if (b_work) memcpy(stg + b_spec + b_fr, sc->h_work.data(), b_work);
-    if ((e = hipMemcpyAsync(sc->specptrs, stg, b_spec, hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(sc->frames_dev, stg + b_spec, b_fr, hipMemcpyHostToDevice, s)) !=
-            hipSuccess)
-        return hip_fail(e, "parameter upload");
-    if (b_work && (e = hipMemcpyAsync(sc->work, stg + b_spec + b_fr, b_work,
-                                      hipMemcpyHostToDevice, s)) != hipSuccess)
-        return hip_fail(e, "work upload");
-    if ((e = hipEventRecord(sc->staged, s)) != hipSuccess) return hip_fail(e, "event");
-    sc->staged_valid = true;
 
     bool any_noise = false;
     for (int i = 0; i < n; ++i) any_noise |= reqs[i].poisson != 0;
@@ -871,7 +919,7 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
     if ((e = hipMemcpyAsync(sc->err_host, sc->err, sizeof(int), hipMemcpyDeviceToHost, s)) !=
         hipSuccess)
         return hip_fail(e, "error word");
-    bool all_async = true;
+    bool all_async = !noalloc;
     for (int i = 0; i < n; ++i)
         all_async &= (reqs[i].flags & E2E_FLAG_ASYNC) && reqs[i].out_on_device &&
                      reqs[i].spectra_on_device;
@@ -893,7 +941,13 @@ e2e_status e2e::check_err_word(int w)
 
 extern "C" e2e_status e2e_render(e2e_ctx *ctx, const e2e_render_req *req)
 {
-    return run_frames(ctx, req, 1, false, nullptr);
+    return run_frames(ctx, req, 1, false);
+}
+
+extern "C" e2e_status e2e_render_noalloc(e2e_ctx *ctx, const e2e_render_req *req)
+{
+    if (!req) return fail(E2E_EINVAL, "e2e_render_noalloc: req is NULL");
+    return run_frames(ctx, req, 1, false, true);
 }
 
 std::string e2e::tune_key(const FormatRes *f, const PsfRes *p, int precision, int spectrum_dtype)
@@ -967,7 +1021,7 @@ extern "C" e2e_status e2e_autotune(e2e_ctx *ctx, const e2e_render_req *reqs, int
             double ms = 1e300;
             for (int rep_i = 0; rep_i < 3 && st == E2E_OK; ++rep_i) {
                 hipEventRecord(e0, s);
-                st = run_frames(ctx, rq.data(), n, batch, nullptr);
+                st = run_frames(ctx, rq.data(), n, batch);
                 hipEventRecord(e1, s);
                 hipEventSynchronize(e1);
                 float f = 0.f;
@@ -1005,7 +1059,7 @@ extern "C" e2e_status e2e_autotune(e2e_ctx *ctx, const e2e_render_req *reqs, int
 extern "C" e2e_status e2e_render_batch(e2e_ctx *ctx, const e2e_render_req *reqs, int32_t n)
 {
     if (!reqs) return fail(E2E_EINVAL, "e2e_render_batch: reqs is NULL");
-    return run_frames(ctx, reqs, n, true, nullptr);
+    return run_frames(ctx, reqs, n, true);
 }
 
 // ------------------------------------------------------------------ noise

@@ -68,6 +68,17 @@ struct Scratch {
     std::map<std::string, GraphRec> graphs;
 };
 
+// Device memory of the allocation-free render (e2e_render_noalloc): the
+// planner output, frame record, spectrum pointers, error word and queue
+// counter of one frame, carved from a file-scope device array whose address
+// e2e_create looks up once for its device.
+constexpr size_t kNoAllocBytes = 16u << 20;
+constexpr int kNoAllocSlots = 64;   // spectrum slots the parameter kernel carries
+struct NoAlloc {
+    char *base = nullptr;           // device address of the array on ctx->dev
+    int err_host = 0;               // host copy of the error word
+};
+
 struct ProfRec {
     std::string name;
     hipEvent_t a = nullptr, b = nullptr;
@@ -101,6 +112,7 @@ struct e2e_ctx {
     std::map<std::string, std::pair<int64_t, double>> prof_acc;
     std::chrono::steady_clock::time_point t0;
     e2e::Server *srv = nullptr;  // owned by serve.cpp
+    e2e::NoAlloc noalloc;        // the allocation-free render's device array
     std::map<std::string, e2e::TuneRec> tune;  // by workload shape (guarded by mu)
     std::mutex srv_mu;
 };
@@ -114,7 +126,7 @@ Scratch *scratch_for(e2e_ctx *ctx, hipStream_t s);
 e2e_status validate_req(e2e_ctx *ctx, const e2e_render_req *r, FormatRes **pf, PsfRes **pp);
 // Render n frames (batch: one persistent launch).  Caller must not hold mu.
 e2e_status run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool batch,
-                      int *unused);
+                      bool noalloc = false);
 e2e_status check_err_word(int w);
 std::string tune_key(const FormatRes *f, const PsfRes *p, int precision, int spectrum_dtype);
 void prof_begin(e2e_ctx *ctx, hipStream_t s, const char *name);

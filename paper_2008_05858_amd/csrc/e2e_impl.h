@@ -144,6 +144,16 @@ hipError_t launch_noise_frames(const FrameDev *frames_dev, const FrameDev *frame
 hipError_t launch_philox(uint64_t seed, uint32_t frame, uint64_t pixel0, int64_t n,
                          uint32_t blocks, uint32_t *out, hipStream_t s);
 hipError_t launch_fill_i32(int *p, int n, int v, hipStream_t s);
+// Writes one frame record and up to kParamSlots spectrum pointers into device
+// memory from a kernel argument (no host staging buffer).
+constexpr int kParamSlots = 64;
+struct FrameParams {
+    FrameDev f;
+    int32_t nslots;
+    const void *spec[kParamSlots];
+};
+hipError_t launch_put_params(const FrameParams &p, FrameDev *frame_dst, const void **spec_dst,
+                             hipStream_t s);
 hipError_t launch_detector(const void *frame, int f64, const float *prnu, int nx, int ny,
                            double dark, int shot, const double *xtalk, double ron, double gain,
                            double bias, int bits, uint64_t seed, uint32_t fidx, uint16_t *adu,

@@ -123,7 +123,22 @@ __global__ void k_fill_i32(int *p, int n, int v)
     if (i < n) p[i] = v;
 }
 
+// Copies the frame record and spectrum pointers carried in the argument.
+__global__ void k_put_params(FrameParams p, FrameDev *frame_dst, const void **spec_dst)
+{
+    const int t = threadIdx.x;
+    if (t < p.nslots) spec_dst[t] = p.spec[t];
+    if (t == 0) *frame_dst = p.f;
+}
+
 }  // namespace
+
+hipError_t launch_put_params(const FrameParams &p, FrameDev *frame_dst, const void **spec_dst,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_put_params, dim3(1), dim3(kParamSlots), 0, s, p, frame_dst, spec_dst);
+    return hipGetLastError();
+}
 
 hipError_t launch_plan(const FrameDev *frames_dev, const FrameDev *frames_host, int n_frames,
                        int *err, hipStream_t s)

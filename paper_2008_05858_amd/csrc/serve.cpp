@@ -195,7 +195,7 @@ static void loop(e2e_ctx *ctx, Server *S)
             }
             if (f.launch_status == E2E_OK) {
                 lk.unlock();
-                f.launch_status = run_frames(ctx, rr.data(), (int)rr.size(), true, nullptr);
+                f.launch_status = run_frames(ctx, rr.data(), (int)rr.size(), true);
                 lk.lock();
             }
             if (f.launch_status == E2E_OK) {

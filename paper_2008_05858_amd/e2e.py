@@ -28,7 +28,8 @@ STATUS_NAMES = {0: "E2E_OK", 1: "E2E_PENDING", -1: "E2E_EINVAL", -2: "E2E_EFORMA
                 -10: "E2E_EINTERNAL"}
 
 EXPORTS = ["e2e_create", "e2e_destroy", "e2e_last_error", "e2e_version", "e2e_format_load",
-           "e2e_psf_load", "e2e_format_free", "e2e_psf_free", "e2e_render", "e2e_render_batch",
+           "e2e_psf_load", "e2e_format_free", "e2e_psf_free", "e2e_render", "e2e_render_noalloc",
+           "e2e_render_batch",
            "e2e_serve_start", "e2e_serve_submit", "e2e_serve_poll", "e2e_serve_stop",
            "e2e_noise_poisson", "e2e_philox_blocks", "e2e_set_profiling", "e2e_kernel_time",
            "e2e_reset_kernel_time", "e2e_autotune", "e2e_detector", "e2e_extract", "e2e_ccf"]
@@ -134,6 +135,7 @@ def lib():
         L.e2e_format_free.argtypes = [C.c_void_p, C.c_uint64]
         L.e2e_psf_free.argtypes = [C.c_void_p, C.c_uint64]
         L.e2e_render.argtypes = [C.c_void_p, P(e2e_render_req)]
+        L.e2e_render_noalloc.argtypes = [C.c_void_p, P(e2e_render_req)]
         L.e2e_render_batch.argtypes = [C.c_void_p, P(e2e_render_req), C.c_int32]
         L.e2e_serve_start.argtypes = [C.c_void_p, P(e2e_serve_config)]
         L.e2e_serve_submit.argtypes = [C.c_void_p, P(e2e_render_req), P(C.c_uint64)]
@@ -208,6 +210,10 @@ def e2e_psf_free(ctx, pid):
 
 def e2e_render(ctx, req):
     return check(lib().e2e_render(ctx, C.byref(req)))
+
+
+def e2e_render_noalloc(ctx, req):
+    return check(lib().e2e_render_noalloc(ctx, C.byref(req)))
 
 
 def e2e_render_batch(ctx, reqs):
