@@ -164,13 +164,18 @@ typedef struct {
     uint32_t flags;
 } e2e_render_req;
 
-/* Per-request timing of the serve loop; times in microseconds since the
- * context was created. */
+/* Per-request timing of the serve loop.  t_*_us: host clock, microseconds
+ * since the context was created.  t_gpu_start_us / t_gpu_end_us: device
+ * timestamps (HIP events on the launch's stream, just before its first and
+ * after its last kernel), microseconds since the serve loop started; the
+ * launches of two requests overlapped on the device when one's start lies
+ * before the other's end. */
 typedef struct {
     double t_submit_us, t_admit_us, t_launch_us, t_done_us;
     uint64_t footprint_bytes;
     int32_t status;
     int32_t batch_size;           /* requests that shared its launch          */
+    double t_gpu_start_us, t_gpu_end_us;
 } e2e_render_stats;
 
 typedef struct {
@@ -236,6 +241,16 @@ e2e_status e2e_render_noalloc(e2e_ctx *ctx, const e2e_render_req *req);
 e2e_status e2e_render_batch(e2e_ctx *ctx, const e2e_render_req *reqs, int32_t n);
 
 /*
+ * Waits for hip_stream (NULL: the context's stream) and reports the device
+ * consistency checks of every render launched on it since the last
+ * synchronous call: E2E_EINTERNAL (message names the check) if any failed,
+ * then clears them.  A synchronous e2e_render / e2e_render_batch on the same
+ * stream reports them the same way; an E2E_FLAG_ASYNC call never does.
+ * Errors: E2E_EINVAL (NULL ctx), E2E_EDEVICE, E2E_EINTERNAL.
+ */
+e2e_status e2e_sync(e2e_ctx *ctx, void *hip_stream);
+
+/*
  * Continuous-batching request loop (Sec. 3's "size the problem, allocate
  * resources, distribute the work", on one GPU).  e2e_serve_start is
  * optional (defaults apply on first submit).  submit copies the request;
@@ -245,6 +260,11 @@ e2e_status e2e_render_batch(e2e_ctx *ctx, const e2e_render_req *reqs, int32_t n)
  * timeout_ms (0 = no wait, <0 = forever) and returns E2E_OK, E2E_PENDING or
  * the request's error; after a non-pending result the ticket is released.
  * Submit and poll are thread-safe.  e2e_serve_stop drains and joins.
+ * Launches on different streams overlap on the device only if those streams
+ * sit on different hardware queues: HIP gives a process GPU_MAX_HW_QUEUES of
+ * them (4 unless set before HIP starts) and assigns streams round-robin, so a
+ * process that uses many streams should raise it (the tests and benchmark
+ * use 16).
  */
 e2e_status e2e_serve_start(e2e_ctx *ctx, const e2e_serve_config *cfg);
 e2e_status e2e_serve_submit(e2e_ctx *ctx, const e2e_render_req *req, e2e_ticket *out);

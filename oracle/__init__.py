@@ -81,6 +81,22 @@ def lib():
     return _lib
 
 
+_lib_omp = None
+
+
+def lib_omp():
+    """The multi-core driver (oracle_omp.c): the same arithmetic, traces over threads."""
+    global _lib_omp
+    if _lib_omp is None:
+        _build.build(force=False)
+        L = C.CDLL(_build.LIB_OMP)
+        L.orc_render_omp.argtypes = [C.POINTER(_Scene), C.POINTER(_Psf), C.c_double,
+                                     C.c_double, C.c_int, C.c_int, C.POINTER(C.c_double),
+                                     C.c_int]
+        _lib_omp = L
+    return _lib_omp
+
+
 def _ptr(a, ct):
     return a.ctypes.data_as(C.POINTER(ct))
 
@@ -152,6 +168,21 @@ def render(sc, req=None, traces=None):
                           _ptr(out, C.c_double))
     if rc != 0:
         raise RuntimeError("oracle render failed")
+    return out
+
+
+def render_omp(sc, req=None, traces=None, threads=0):
+    """Full FP64 frame by the multi-core driver: traces over `threads` OpenMP
+    threads (0: all), each in its own row band, bands added in trace order."""
+    rv = req.rv_mps if req is not None else 0.0
+    fs = req.flux_scale if req is not None else 1.0
+    m = _Marshalled(sc)
+    lo, hi = (0, len(sc.traces)) if traces is None else traces
+    out = np.zeros((sc.ny, sc.nx), np.float64)
+    rc = lib_omp().orc_render_omp(C.byref(m.scene), C.byref(m.psf), rv, fs, lo, hi,
+                                  _ptr(out, C.c_double), int(threads))
+    if rc != 0:
+        raise RuntimeError("oracle render (multi-core) failed")
     return out
 
 

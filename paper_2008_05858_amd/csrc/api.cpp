@@ -524,10 +524,12 @@ Scratch *e2e::scratch_for(e2e_ctx *ctx, hipStream_t s)
     auto *sc = new Scratch();
     if (hipMalloc(&sc->err, sizeof(int)) != hipSuccess ||
         hipMalloc(&sc->counter, sizeof(int)) != hipSuccess ||
-        hipHostMalloc((void **)&sc->err_host, sizeof(int)) != hipSuccess) {
+        hipHostMalloc((void **)&sc->err_host, sizeof(int)) != hipSuccess ||
+        launch_fill_i32(sc->err, 1, 0, s) != hipSuccess) {
         free_scratch(sc);
         return nullptr;
     }
+    *sc->err_host = 0;
     ctx->scratch[s] = sc;
     return sc;
 }
@@ -836,6 +838,8 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
         sc->staged_valid = true;
     }
 
+    if (noalloc && (e = launch_fill_i32(sc->err, 1, 0, s)) != hipSuccess)
+        return hip_fail(e, "error word");
     bool any_noise = false;
     for (int i = 0; i < n; ++i) any_noise |= reqs[i].poisson != 0;
     const int2 *work = batch ? sc->work : nullptr;
@@ -843,7 +847,8 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
     // the launch sequence: clear error word and queue counter, plan, render, noise
     auto enqueue = [&]() -> hipError_t {
         hipError_t q;
-        if ((q = launch_fill_i32(sc->err, 1, 0, s)) != hipSuccess) return q;
+        // the error word is sticky (cleared after a synchronous read), so an
+        // asynchronous launch's device error reaches the next synchronous call
         if ((q = launch_fill_i32(sc->counter, 1, 0, s)) != hipSuccess) return q;
         prof_begin(ctx, s, "plan");
         q = launch_plan(sc->frames_dev, sc->h_frames.data(), n, sc->err, s);
@@ -925,7 +930,39 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
                      reqs[i].spectra_on_device;
     if (all_async) return E2E_OK;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "render");
-    return check_err_word(*sc->err_host);
+    return take_err_word(sc, s);
+}
+
+// The device error word of a stream's scratch after the stream has passed
+// the copy into err_host: reported (also for the asynchronous launches since
+// the last synchronous read) and cleared.
+e2e_status e2e::take_err_word(Scratch *sc, hipStream_t s)
+{
+    const int w = *sc->err_host;
+    if (w == 0) return E2E_OK;
+    *sc->err_host = 0;
+    launch_fill_i32(sc->err, 1, 0, s);
+    return check_err_word(w);
+}
+
+extern "C" e2e_status e2e_sync(e2e_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return fail(E2E_EINVAL, "e2e_sync: NULL context");
+    hipSetDevice(ctx->dev);
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->scratch.find(s);
+    hipError_t e;
+    if (it == ctx->scratch.end()) {
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "e2e_sync");
+        return E2E_OK;
+    }
+    Scratch *sc = it->second;
+    if ((e = hipMemcpyAsync(sc->err_host, sc->err, sizeof(int), hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "e2e_sync");
+    return take_err_word(sc, s);
 }
 
 e2e_status e2e::check_err_word(int w)

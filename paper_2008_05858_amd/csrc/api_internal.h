@@ -128,6 +128,7 @@ e2e_status validate_req(e2e_ctx *ctx, const e2e_render_req *r, FormatRes **pf, P
 e2e_status run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool batch,
                       bool noalloc = false);
 e2e_status check_err_word(int w);
+e2e_status take_err_word(Scratch *sc, hipStream_t s);
 std::string tune_key(const FormatRes *f, const PsfRes *p, int precision, int spectrum_dtype);
 void prof_begin(e2e_ctx *ctx, hipStream_t s, const char *name);
 void prof_end(e2e_ctx *ctx, hipStream_t s);

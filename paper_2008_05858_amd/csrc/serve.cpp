@@ -28,6 +28,7 @@ struct SReq {
     std::vector<size_t> spec_bytes;
     std::vector<void *> dev_owned;         // device buffers freed on completion
     void *user_out = nullptr;
+    void *out_stage = nullptr;             // pinned copy of the frame (host output)
     size_t out_bytes = 0;
     uint64_t footprint = 0;
     FormatRes *fmt = nullptr;
@@ -40,7 +41,7 @@ struct SReq {
 
 struct Flight {
     int stream = -1;
-    hipEvent_t ev = nullptr;
+    hipEvent_t ev0 = nullptr, ev = nullptr;  // before the first, after the last kernel
     std::vector<SReq *> reqs;
     e2e_status launch_status = E2E_OK;
 };
@@ -55,6 +56,7 @@ struct Server {
     std::map<e2e_ticket, SReq *> all;
     std::vector<hipStream_t> streams;
     std::vector<bool> stream_busy;
+    hipEvent_t ref = nullptr;              // device time zero of the loop
     uint64_t reserved = 0;
     int admitted = 0;
     e2e_ticket next = 1;
@@ -63,19 +65,28 @@ struct Server {
 
 }  // namespace e2e
 
-static void finish(e2e_ctx *ctx, Server *S, SReq *q, e2e_status st)
+// Device and host buffers of a finished request, released without S->m held
+// (hipFree can wait on other streams' work).
+static void release(SReq *q)
 {
     for (void *p : q->dev_owned) hipFree(p);
     q->dev_owned.clear();
     for (void *p : q->host_stage) hipHostFree(p);
     q->host_stage.clear();
+    if (q->out_stage) hipHostFree(q->out_stage);
+    q->out_stage = nullptr;
+}
+
+// Bookkeeping of a finished request (S->m held).
+static void finish(e2e_ctx *ctx, Server *S, SReq *q, e2e_status st, const std::string &msg)
+{
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         if (q->fmt) q->fmt->refs--;
         if (q->psf) q->psf->refs--;
     }
     q->st.t_done_us = now_us(ctx);
-    if (st != E2E_OK) q->msg = e2e_last_error();
+    q->msg = msg;
     q->st.status = st;
     q->status = st;
     q->done = true;
@@ -83,7 +94,8 @@ static void finish(e2e_ctx *ctx, Server *S, SReq *q, e2e_status st)
     S->admitted -= 1;
 }
 
-// Upload host spectra and allocate a device frame for an admitted request.
+// Upload host spectra and allocate device (and pinned) frames for an
+// admitted request; called without S->m held.
 static e2e_status stage_in(SReq *q, hipStream_t s)
 {
     hipError_t e;
@@ -102,6 +114,10 @@ static e2e_status stage_in(SReq *q, hipStream_t s)
         if ((e = hipMalloc(&d, q->out_bytes)) != hipSuccess) return hip_fail(e, "serve frame");
         q->dev_owned.push_back(d);
         q->r.out = d;
+        if ((e = hipHostMalloc(&q->out_stage, q->out_bytes)) != hipSuccess) {
+            q->out_stage = nullptr;
+            return hip_fail(e, "serve frame staging");
+        }
     }
     q->r.spectra = q->specs.data();
     q->r.spectra_on_device = 1;
@@ -111,13 +127,47 @@ static e2e_status stage_in(SReq *q, hipStream_t s)
     return E2E_OK;
 }
 
+// Requests of one launch: the queue head, then later requests of the same
+// PSF kind / table size / precision / spectrum type (look-ahead, queue order
+// kept), while slots and memory last.  S->m held.
+static std::vector<SReq *> take_group(e2e_ctx *ctx, Server *S, uint64_t avail)
+{
+    std::vector<SReq *> group;
+    for (auto it = S->queue.begin(); it != S->queue.end() &&
+                                     (int)group.size() < S->cfg.max_batch &&
+                                     S->admitted < S->cfg.max_inflight;) {
+        SReq *q = *it;
+        if (!group.empty()) {
+            const SReq *g0 = group[0];
+            if (q->psf->kind != g0->psf->kind || q->psf->kw != g0->psf->kw ||
+                q->r.precision != g0->r.precision ||
+                q->r.spectrum_dtype != g0->r.spectrum_dtype) {
+                ++it;
+                continue;
+            }
+        }
+        if (S->reserved + q->footprint > avail) {
+            if (group.empty()) break;  // the head waits for memory; nothing overtakes it
+            ++it;
+            continue;
+        }
+        it = S->queue.erase(it);
+        S->reserved += q->footprint;
+        S->admitted += 1;
+        q->st.t_admit_us = now_us(ctx);
+        group.push_back(q);
+    }
+    return group;
+}
+
 static void loop(e2e_ctx *ctx, Server *S)
 {
     hipSetDevice(ctx->dev);
     std::unique_lock<std::mutex> lk(S->m);
     for (;;) {
-        // reap finished launches
-        bool progressed = false;
+        // reap finished launches: take them out under the lock, copy frames
+        // and free buffers without it, then publish the results
+        std::vector<Flight> done;
         for (size_t i = 0; i < S->flights.size();) {
             Flight &f = S->flights[i];
             hipError_t q = f.launch_status == E2E_OK ? hipEventQuery(f.ev) : hipSuccess;
@@ -125,27 +175,47 @@ static void loop(e2e_ctx *ctx, Server *S)
                 ++i;
                 continue;
             }
-            e2e_status st = f.launch_status;
-            if (st == E2E_OK && q != hipSuccess) st = hip_fail(q, "serve launch");
-            if (st == E2E_OK) {
-                Scratch *sc = scratch_for(ctx, S->streams[f.stream]);
-                st = sc ? check_err_word(*sc->err_host) : E2E_EDEVICE;
-            }
-            for (SReq *r : f.reqs) {
-                if (st == E2E_OK && r->user_out) {
-                    hipError_t e = hipMemcpy(r->user_out, r->r.out, r->out_bytes,
-                                             hipMemcpyDeviceToHost);
-                    finish(ctx, S, r, e == hipSuccess ? E2E_OK : hip_fail(e, "serve download"));
-                } else {
-                    finish(ctx, S, r, st);
-                }
-            }
-            if (f.ev) hipEventDestroy(f.ev);
+            if (f.launch_status == E2E_OK && q != hipSuccess) f.launch_status = hip_fail(q, "serve launch");
             S->stream_busy[f.stream] = false;
+            done.push_back(f);
             S->flights.erase(S->flights.begin() + i);
-            progressed = true;
         }
-        if (progressed) S->cv_done.notify_all();
+        if (!done.empty()) {
+            lk.unlock();
+            std::vector<std::pair<e2e_status, std::string>> res;
+            for (Flight &f : done) {
+                e2e_status st = f.launch_status;
+                if (st == E2E_OK) {
+                    std::lock_guard<std::mutex> g(ctx->mu);
+                    Scratch *sc = scratch_for(ctx, S->streams[f.stream]);
+                    st = sc ? take_err_word(sc, S->streams[f.stream]) : E2E_EDEVICE;
+                }
+                std::string msg = st != E2E_OK ? e2e_last_error() : "";
+                float a = 0.f, b = 0.f;
+                if (f.ev0 && f.ev && hipEventElapsedTime(&a, S->ref, f.ev0) == hipSuccess &&
+                    hipEventElapsedTime(&b, S->ref, f.ev) == hipSuccess) {
+                    for (SReq *r : f.reqs) {
+                        r->st.t_gpu_start_us = 1e3 * (double)a;
+                        r->st.t_gpu_end_us = 1e3 * (double)b;
+                    }
+                }
+                for (SReq *r : f.reqs) {
+                    if (st == E2E_OK && r->user_out) memcpy(r->user_out, r->out_stage, r->out_bytes);
+                    release(r);
+                    res.emplace_back(st, msg);
+                }
+                if (f.ev0) hipEventDestroy(f.ev0);
+                if (f.ev) hipEventDestroy(f.ev);
+            }
+            lk.lock();
+            size_t k = 0;
+            for (Flight &f : done)
+                for (SReq *r : f.reqs) {
+                    finish(ctx, S, r, res[k].first, res[k].second);
+                    ++k;
+                }
+            S->cv_done.notify_all();
+        }
 
         // admit and launch while a stream, slots and memory are free
         for (;;) {
@@ -159,50 +229,42 @@ static void loop(e2e_ctx *ctx, Server *S)
                 std::lock_guard<std::mutex> g(ctx->mu);
                 avail = ctx->budget > ctx->used ? ctx->budget - ctx->used : 0;
             }
-            std::vector<SReq *> group;
-            while (!S->queue.empty() && (int)group.size() < S->cfg.max_batch &&
-                   S->admitted < S->cfg.max_inflight) {
-                SReq *q = S->queue.front();
-                if (!group.empty()) {
-                    const SReq *g0 = group[0];
-                    if (q->psf->kind != g0->psf->kind || q->psf->kw != g0->psf->kw ||
-                        q->r.precision != g0->r.precision ||
-                        q->r.spectrum_dtype != g0->r.spectrum_dtype)
-                        break;
-                }
-                if (S->reserved + q->footprint > avail) break;
-                S->queue.pop_front();
-                S->reserved += q->footprint;
-                S->admitted += 1;
-                q->st.t_admit_us = now_us(ctx);
-                group.push_back(q);
-            }
+            std::vector<SReq *> group = take_group(ctx, S, avail);
             if (group.empty()) break;
+            S->stream_busy[si] = true;
             Flight f;
             f.stream = si;
             f.reqs = group;
             hipStream_t s = S->streams[si];
+            lk.unlock();
             std::vector<e2e_render_req> rr;
             for (SReq *q : group) {
                 e2e_status st = stage_in(q, s);
                 if (st != E2E_OK) f.launch_status = st;
                 rr.push_back(q->r);
             }
-            double tl = now_us(ctx);
+            const double tl = now_us(ctx);
             for (SReq *q : group) {
                 q->st.t_launch_us = tl;
                 q->st.batch_size = (int32_t)group.size();
             }
             if (f.launch_status == E2E_OK) {
-                lk.unlock();
+                hipEventCreate(&f.ev0);
+                hipEventRecord(f.ev0, s);
                 f.launch_status = run_frames(ctx, rr.data(), (int)rr.size(), true);
-                lk.lock();
             }
             if (f.launch_status == E2E_OK) {
-                hipEventCreateWithFlags(&f.ev, hipEventDisableTiming);
+                // host frames come back on the same stream, before the event
+                for (SReq *q : group) {
+                    if (!q->user_out) continue;
+                    hipError_t e = hipMemcpyAsync(q->out_stage, q->r.out, q->out_bytes,
+                                                  hipMemcpyDeviceToHost, s);
+                    if (e != hipSuccess) f.launch_status = hip_fail(e, "serve download");
+                }
+                hipEventCreate(&f.ev);
                 hipEventRecord(f.ev, s);
             }
-            S->stream_busy[si] = true;
+            lk.lock();
             S->flights.push_back(f);
         }
 
@@ -238,6 +300,12 @@ extern "C" e2e_status e2e_serve_start(e2e_ctx *ctx, const e2e_serve_config *cfg)
         }
         S->streams.push_back(s);
         S->stream_busy.push_back(false);
+    }
+    hipError_t e = hipEventCreate(&S->ref);
+    if (e == hipSuccess) e = hipEventRecord(S->ref, S->streams[0]);
+    if (e != hipSuccess) {
+        for (auto q : S->streams) hipStreamDestroy(q);
+        return hip_fail(e, "serve reference event");
     }
     Server *raw = S.release();
     ctx->srv = raw;
@@ -370,5 +438,6 @@ extern "C" e2e_status e2e_serve_stop(e2e_ctx *ctx)
         hipStreamSynchronize(s);
         hipStreamDestroy(s);
     }
+    if (S->ref) hipEventDestroy(S->ref);
     return E2E_OK;
 }

@@ -32,7 +32,8 @@ EXPORTS = ["e2e_create", "e2e_destroy", "e2e_last_error", "e2e_version", "e2e_fo
            "e2e_render_batch",
            "e2e_serve_start", "e2e_serve_submit", "e2e_serve_poll", "e2e_serve_stop",
            "e2e_noise_poisson", "e2e_philox_blocks", "e2e_set_profiling", "e2e_kernel_time",
-           "e2e_reset_kernel_time", "e2e_autotune", "e2e_detector", "e2e_extract", "e2e_ccf"]
+           "e2e_reset_kernel_time", "e2e_autotune", "e2e_detector", "e2e_extract", "e2e_ccf",
+           "e2e_sync"]
 E2E_TUNE_MAX = 16
 
 
@@ -91,7 +92,8 @@ class e2e_render_stats(C.Structure):
     _fields_ = [("t_submit_us", C.c_double), ("t_admit_us", C.c_double),
                 ("t_launch_us", C.c_double), ("t_done_us", C.c_double),
                 ("footprint_bytes", C.c_uint64), ("status", C.c_int32),
-                ("batch_size", C.c_int32)]
+                ("batch_size", C.c_int32), ("t_gpu_start_us", C.c_double),
+                ("t_gpu_end_us", C.c_double)]
 
 
 class e2e_serve_config(C.Structure):
@@ -136,6 +138,7 @@ def lib():
         L.e2e_psf_free.argtypes = [C.c_void_p, C.c_uint64]
         L.e2e_render.argtypes = [C.c_void_p, P(e2e_render_req)]
         L.e2e_render_noalloc.argtypes = [C.c_void_p, P(e2e_render_req)]
+        L.e2e_sync.argtypes = [C.c_void_p, C.c_void_p]
         L.e2e_render_batch.argtypes = [C.c_void_p, P(e2e_render_req), C.c_int32]
         L.e2e_serve_start.argtypes = [C.c_void_p, P(e2e_serve_config)]
         L.e2e_serve_submit.argtypes = [C.c_void_p, P(e2e_render_req), P(C.c_uint64)]
@@ -214,6 +217,10 @@ def e2e_render(ctx, req):
 
 def e2e_render_noalloc(ctx, req):
     return check(lib().e2e_render_noalloc(ctx, C.byref(req)))
+
+
+def e2e_sync(ctx, stream=None):
+    return check(lib().e2e_sync(ctx, stream))
 
 
 def e2e_render_batch(ctx, reqs):

@@ -58,23 +58,85 @@ def test_c1_batch_sampled():
     ld.free()
 
 
-def test_c3_uneven_batch_sampled():
-    from paper_2008_05858_amd import Loaded
+def _strat_check(name, sc, rq, g, tw=56, th=32, n_each=25, seed=0):
+    """Parity at stratified pixels: tile-boundary and carry rows, tile-column
+    edges, node-cell boundary lines, bright pixels, trace ends, anywhere."""
+    from workloads import metrics
+    gx, gy = int(sc.psf.gx), int(sc.psf.gy)
+    nxl = [m * (sc.nx - 1) / (gx - 1) for m in range(gx)] if gx > 1 else []
+    nyl = [m * (sc.ny - 1) / (gy - 1) for m in range(gy)] if gy > 1 else []
+    px, py = metrics.stratified_pixels(g, tw, th, node_x=nxl, node_y=nyl, n_each=n_each,
+                                       seed=seed)
+    o = oracle.render_pixels(sc, rq, px, py)
+    peak = float(g.max())
+    err = float(np.max(np.abs(g[py, px] - o)) / peak)
+    print(f"[{name}] {len(px)} stratified px: max|dF|/peak = {err:.3e} (peak {peak:.4g})",
+          flush=True)
+    return err, len(px)
+
+
+def test_c3_configured_batch():
+    """The batched configuration as configured: 64 renders of uneven size in
+    one persistent launch (captured graph), 32 ESPRESSO-shaped 9216^2 frames
+    and 32 of the 4096^2 40-order 1-fiber variant in a seeded order, each with
+    its own Doppler shift (U[-10, 10] m/s) and exposure (U[1e3, 1e5]),
+    Poisson noise on every other frame.  Checked: stratified oracle parity on
+    four noiseless frames, bitwise equality with single renders on four
+    frames, and the noisy frames equal to e2e_noise_poisson applied to the
+    noiseless single render (same seed and frame index)."""
+    import torch
+    import paper_2008_05858_amd as P
+    from paper_2008_05858_amd import e2e as E
     gu = _gu()
+    ctx = gu.ctx()
     a, b = scene("c1"), scene("c3v")
-    la, lb = Loaded(gu.ctx(), a), Loaded(gu.ctx(), b)
-    rqs = [Request(rv_mps=3.3, flux_scale=9.0), Request(rv_mps=-4.4, flux_scale=0.2),
-           Request(rv_mps=0.7, flux_scale=5.0)]
-    print("case c3: c1 + 2 x 4096^2 variant frames in one launch", flush=True)
-    outs = gu.render_batch([b, a, b], rqs, [lb, la, lb])
-    assert _check("c3 variant 0", b, rqs[0], outs[0], n_bright=80, n_rand=20, seed=3) < TOL
-    assert _check("c3 c1", a, rqs[1], outs[1], n_bright=80, n_rand=20, seed=4) < TOL
-    assert _check("c3 variant 1", b, rqs[2], outs[2], n_bright=80, n_rand=20, seed=5) < TOL
+    la, lb = P.Loaded(ctx, a), P.Loaded(ctx, b)
+    spa, sdt = gu.device_spectra(a)
+    spb, _ = gu.device_spectra(b)
+    rng = np.random.Generator(np.random.PCG64(1003))
+    kinds = rng.permutation(np.array([0] * 32 + [1] * 32))
+    outs, rr, keep, meta = [], [], [], []
+    for f, kd in enumerate(kinds):
+        sc, ld, sp = (a, la, spa) if kd == 0 else (b, lb, spb)
+        rq = Request(rv_mps=float(rng.uniform(-10, 10)),
+                     flux_scale=float(rng.uniform(1e3, 1e5) / 1e4), seed=99, frame_index=f,
+                     poisson=bool(f % 2))
+        o, odt = gu.out_tensor(sc)
+        r, k = gu.request_for(ld, sc, sp, sdt, o, odt, rq)
+        outs.append(o)
+        rr.append(r)
+        keep.append(k)
+        meta.append((sc, ld, rq))
+    torch.cuda.synchronize()
+    print("case c3: 64 uneven frames, one persistent launch", flush=True)
+    E.e2e_render_batch(ctx, rr)
+    E.e2e_render_batch(ctx, rr)  # a replay of the captured graph gives the same frames
+    quiet = [f for f in range(64) if f % 2 == 0]
+    noisy = [f for f in range(64) if f % 2 == 1]
+    pick_q = [next(f for f in quiet if kinds[f] == 0), next(f for f in quiet if kinds[f] == 1),
+              [f for f in quiet if kinds[f] == 0][-1], [f for f in quiet if kinds[f] == 1][-1]]
+    for f in pick_q:
+        sc, ld, rq = meta[f]
+        g = outs[f].cpu().numpy()
+        err, n = _strat_check(f"c3 frame {f} ({'c1' if kinds[f] == 0 else 'variant'})", sc, rq,
+                              g, seed=f)
+        assert n >= 150 and err < TOL
+        # bitwise: the same request rendered alone
+        assert np.array_equal(g, gu.render(sc, rq, loaded=ld)), f
+    pick_n = [next(f for f in noisy if kinds[f] == 0), next(f for f in noisy if kinds[f] == 1),
+              [f for f in noisy if kinds[f] == 0][-1], [f for f in noisy if kinds[f] == 1][-1]]
+    for f in pick_n:
+        sc, ld, rq = meta[f]
+        quiet_rq = Request(rv_mps=rq.rv_mps, flux_scale=rq.flux_scale)
+        o, odt = gu.out_tensor(sc)
+        r, k = gu.request_for(ld, sc, spa if kinds[f] == 0 else spb, sdt, o, odt, quiet_rq)
+        E.e2e_render(ctx, r)
+        E.e2e_noise_poisson(ctx, o.data_ptr(), odt, sc.nx * sc.ny, rq.seed, f, 1, None)
+        same = np.array_equal(outs[f].cpu().numpy(), o.cpu().numpy())
+        print(f"  c3 noisy frame {f}: equal to render + e2e_noise_poisson: {same}", flush=True)
+        assert same
     la.free()
     lb.free()
-
-
-SEP_BOUNDS = {"f64": 1e-6, "f32": 2e-5, "f16_hilo": 2e-6, "bf16_hilo": 2e-4}
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16_hilo", "bf16_hilo"])

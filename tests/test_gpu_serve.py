@@ -155,3 +155,47 @@ def test_serve_admission_by_footprint():
     E.e2e_serve_stop(ctx)
     ld.free()
     E.e2e_destroy(ctx)
+
+
+def test_serve_overlap_on_device():
+    """Two requests on two streams of the serve loop: the second is launched,
+    and starts on the device, before the first has finished; each frame is
+    bitwise the one the plain renderer makes alone."""
+    import torch
+    import paper_2008_05858_amd as P
+    from paper_2008_05858_amd import e2e as E
+    gu = _gu()
+    ctx = E.e2e_create(0, 0)
+    sc = scene("mini_table", n_samp=20_000_000)  # 3.2e8 samples: over a millisecond each
+    ld = P.Loaded(ctx, sc)
+    specs, sdt = gu.device_spectra(sc)
+    rqs = [Request(rv_mps=4.0, flux_scale=1.3), Request(rv_mps=-7.0, flux_scale=0.8)]
+    refs = [gu.render(sc, rq, loaded=ld, context=ctx) for rq in rqs]
+    outs, keep = [], []
+    for rq in rqs:
+        o, odt = gu.out_tensor(sc)
+        r, k = gu.request_for(ld, sc, specs, sdt, o, odt, rq)
+        outs.append(o)
+        keep.append((r, k))
+    E.e2e_serve_start(ctx, max_inflight=4, max_queue=16, n_streams=2, max_batch=1)
+    torch.cuda.synchronize()
+    print("case serve overlap on two streams", flush=True)
+    # the first round captures each stream's launch graph; the second is timed
+    for rnd in range(2):
+        tk = [E.e2e_serve_submit(ctx, r) for r, _ in keep]
+        st = []
+        for t in tk:
+            code, s = E.e2e_serve_poll(ctx, t, -1)
+            assert code == E.E2E_OK
+            st.append(s)
+    a, b = st
+    print(f"  launch {a.t_launch_us:.0f} / {b.t_launch_us:.0f} us, done {a.t_done_us:.0f} / "
+          f"{b.t_done_us:.0f} us; device {a.t_gpu_start_us:.0f}-{a.t_gpu_end_us:.0f} and "
+          f"{b.t_gpu_start_us:.0f}-{b.t_gpu_end_us:.0f} us")
+    assert b.t_launch_us < a.t_done_us
+    assert b.t_gpu_start_us < a.t_gpu_end_us and a.t_gpu_start_us < b.t_gpu_end_us
+    for o, ref in zip(outs, refs):
+        assert np.array_equal(o.cpu().numpy(), ref)
+    E.e2e_serve_stop(ctx)
+    ld.free()
+    E.e2e_destroy(ctx)
