@@ -49,7 +49,8 @@ def test_c1_batch_sampled():
     print("case c1 full frame x2, persistent batch", flush=True)
     outs = gu.render_batch([sc, sc], rqs, [ld, ld])
     for b, (g, rq) in enumerate(zip(outs, rqs)):
-        assert _check(f"c1 frame {b}", sc, rq, g, seed=b) < TOL
+        err, n = _strat_check(f"c1 frame {b}", sc, rq, g, n_each=35, seed=b)
+        assert n >= 200 and err < TOL
     # flux: every trace lies on the detector with its whole footprint
     tot = sum(float(sc.spectra[t.slot].astype(np.float64).sum()) * t.thr for t in sc.traces)
     rel = abs(outs[0].astype(np.float64).sum() - tot * rqs[0].flux_scale) / (tot * rqs[0].flux_scale)
@@ -139,13 +140,23 @@ def test_c3_configured_batch():
     lb.free()
 
 
+# bound on max |dF| / peak per precision variant of the separable path at
+# full size: the FP64-summing and fp16 hi/lo paths hold the 1e-6 frame bar;
+# the FP32-summing and bf16 hi/lo ones are held to about twice what they
+# measure (1.1e-6 and 1.4e-6 of the peak)
+SEP_BOUNDS = {"f64": 1e-6, "f32": 2.5e-6, "f16_hilo": 1e-6, "bf16_hilo": 3e-6}
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16_hilo", "bf16_hilo"])
 def test_c2_precision_variants_sampled(prec):
     sc = scene("c2")
     rq = Request(rv_mps=2.0, precision=prec)
     print(f"case c2 full frame, precision {prec}", flush=True)
     g = _gu().render(sc, rq)
-    assert _check(f"c2 {prec}", sc, rq, g, n_bright=120, n_rand=30, seed=7) < SEP_BOUNDS[prec]
+    mfma = prec in ("f16_hilo", "bf16_hilo")
+    err, n = _strat_check(f"c2 {prec}", sc, rq, g, tw=64 if mfma else 16, th=32 if mfma else 16,
+                          seed=7)
+    assert n >= 150 and err < SEP_BOUNDS[prec]
 
 
 def test_c4_hires_sampled():
@@ -153,7 +164,8 @@ def test_c4_hires_sampled():
     rq = Request(rv_mps=-1.0)
     print("case c4 HIRES-shaped full frame", flush=True)
     g = _gu().render(sc, rq)
-    assert _check("c4", sc, rq, g, n_bright=12, n_rand=4, seed=9) < TOL
+    err, n = _strat_check("c4", sc, rq, g, tw=52, th=32, n_each=35, seed=9)
+    assert n >= 200 and err < TOL
 
 
 def test_separable_one_and_two_pixel_kernels_agree_bitwise():

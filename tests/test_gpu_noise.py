@@ -39,7 +39,7 @@ def test_poisson_counts_match_oracle_and_law():
     o = oracle.poisson_frame(means, 99, 4)
     same = np.mean(g == o)
     print(f"identical counts: {same:.6f}", flush=True)
-    assert same > 0.999
+    assert same == 1.0
     for lam in (0.3, 5.0, 9.99, 10.0, 50.0, 1e4, 1e7):
         d = g[means == lam]
         assert abs(d.mean() - lam) < 5 * np.sqrt(lam / d.size)

@@ -176,16 +176,21 @@ def test_doppler_centroid_shift_on_gpu():
 
 
 def test_flux_conservation_gpu():
+    """The frame holds every photon of samples whose footprint is on chip
+    (the superposition of Sec. 2 / Sec. 2.2 loses nothing).  The oracle holds
+    this to 1e-12; the GPU path takes the pixel weights in FP32 on
+    pixel-relative offsets (FP64 sums), so its bound is 1e-6 relative."""
     sc = scene("c0")
     g = _gu().render(sc, Request(flux_scale=2.0))
     tot = sc.spectra[0].sum() * 2.0
     assert abs(g.sum() - tot) / tot < 1e-6
 
 
-# bound on max |dF| / peak per precision variant of the separable path; the
-# FP64-accumulating path meets the 1e-6 frame requirement, the reduced ones
-# are measured and reported (hi/lo bf16 keeps ~16 mantissa bits)
-SEP_BOUNDS = {"f64": 1e-6, "f32": 2e-5, "f16_hilo": 2e-6, "bf16_hilo": 2e-4}
+# bound on max |dF| / peak per precision variant of the separable path: the
+# FP64-summing and fp16 hi/lo paths meet the 1e-6 frame requirement; the
+# FP32-summing and bf16 hi/lo ones (hi/lo bf16 keeps ~16 mantissa bits) are
+# held to about twice what they measure here (2.0e-6 and 1.5e-6)
+SEP_BOUNDS = {"f64": 1e-6, "f32": 4e-6, "f16_hilo": 1e-6, "bf16_hilo": 3e-6}
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16_hilo", "bf16_hilo"])
@@ -203,3 +208,6 @@ def test_separable_precision_variants(prec):
     co = metrics.centroid(o[j0:j + 9, i0:i + 21], i0, j0)
     print(f"  photocentre shift x {cg[0]-co[0]:.2e} px, y {cg[1]-co[1]:.2e} px", flush=True)
     assert err < SEP_BOUNDS[prec]
+    # the paper's photocentre budget (Sec. 1, Sec. 2.2): 1e-5 px
+    assert np.isfinite(cg).all() and np.isfinite(co).all()
+    assert abs(cg[0] - co[0]) <= 1e-5 and abs(cg[1] - co[1]) <= 1e-5

@@ -95,12 +95,14 @@ def test_c5_sfi_full_frame_sampled():
     tot = sum(float(np.sum(sc.spectra[t.slot], dtype=np.float64)) * t.thr for t in sc.traces)
     print(f"[c5_sfi] frame sum {g.sum():.6e}, photons {tot:.6e}", flush=True)
     assert abs(g.sum() / tot - 1) < 1e-5
-    # pixels on traces: the brightest pixel of a few columns of some orders
-    rng = np.random.default_rng(3)
-    px, py = [], []
-    for t in rng.choice(len(sc.traces), 6, replace=False):
-        x, y = oracle.positions(sc, int(t), 500.0, int(rng.integers(2000, 10000)), 1)
-        px.append(int(round(x[0]))); py.append(int(round(y[0])))
+    # stratified pixels: tile-boundary rows, tile-column edges, node-cell
+    # boundary lines, bright pixels, trace ends, anywhere
+    from workloads import metrics
+    gx, gy = int(sc.psf.gx), int(sc.psf.gy)
+    px, py = metrics.stratified_pixels(
+        g, 64, 32, node_x=[m * (sc.nx - 1) / (gx - 1) for m in range(gx)],
+        node_y=[m * (sc.ny - 1) / (gy - 1) for m in range(gy)], n_each=20, seed=3)
+    assert len(px) >= 100
     o = oracle.render_pixels(sc, Request(rv_mps=500.0), px, py)
     gv = g[py, px].astype(np.float64)
     err = np.abs(gv - o).max() / g.max()
@@ -117,10 +119,10 @@ def test_sfi_trace_off_detector_edges():
     print("case mini_sfi trace over the detector edges", flush=True)
     sc = scene("mini_sfi", n_samp=300)
     t = sc.traces[0]
-    # x from -6 to 126 px.  Generic coefficients: with round ones (60 + 66 t)
-    # some samples sit exactly on a half-integer x, where the window anchor
-    # floor(x + 1/2) depends on the last bit of x and the renormalised
-    # window legitimately jumps by the truncated tail (~1e-5 of the peak).
+    # x from -6 to 126 px.  Generic coefficients keep samples off half-integer
+    # x, where the window anchor floor(x + 1/2) depends on the last bit of x
+    # and either window is correct; samples on such ties are checked, with
+    # both choices accepted, in test_gpu_anchor_ties.py.
     t2 = dataclasses.replace(t, cx=[60.0123, 66.0371], cy=[1.3117, 0.4029])
     sc = dataclasses.replace(sc, traces=[t2])
     g = _gu().render(sc)
