@@ -9,8 +9,9 @@
 // axis) evaluates the sample's pixel integrals on the tile's columns (times
 // phi) or rows and stores them in LDS already in operand layout: one line
 // of 128 samples per tile column / row, so an operand fragment (8
-// consecutive samples of one pixel line) is one 16-byte read.  Each value is
-// split into hi + lo halves (hi = round(v), lo = round(v - hi)) in two
+// consecutive samples of one pixel line) is one 16-byte read.  The normal
+// CDF at the pixel edges comes from fitted FP32 forms good to about one ulp
+// of 1/2 (phi_lower_f32).  Each value is split into hi + lo halves (hi = round(v), lo = round(v - hi)) in two
 // planes.  Entries outside a sample's window are zero: a thread clears what
 // its sample slot held in the previous chunk and the new window does not
 // cover (128 samples move a window by about a pixel, so one or two lines).
@@ -66,45 +67,42 @@ __device__ __forceinline__ int lds_at(int p, int s)
 
 // One sample's pixel integrals on NL consecutive pixel lines: window pixel m
 // (0 .. 2H, at line off + m) gets (Phi(e_{m+1}) - Phi(e_m)) / norm * scale,
-// e_m = (m - H - 1/2 - d) / sg, through c_m = Phi(-|e_m|) as in the VALU
-// path (outer edges by the fitted tail, inner ones by erfcf).  Writes the
-// in-tile entries of both planes; returns the written line range.
+// e_m = (m - H - 1/2 - d) / sg, norm = Phi(e_{2H+1}) - Phi(e_0).  Each edge
+// is one c_m = Phi(-|e_m|) (phi_lower_f32), and each difference is taken
+// on the side of the centre where it does not cancel.  Writes the in-tile
+// entries of both planes and returns the written line range.
 template <int NL, typename E>
 __device__ __forceinline__ void stage_axis(float d, float sg, int H, float scale, int off, int s,
                                            unsigned short *hi, unsigned short *lo, int *plo,
                                            int *phi_)
 {
     const float inv = 1.0f / sg;
-    const float c0 = phi_tail_f32(((float)(0 - H) - 0.5f - d) * inv);
-    const float clast = phi_tail_f32(((float)(H + 1) - 0.5f - d) * inv);
+    const float c0 = phi_lower_f32(((float)(0 - H) - 0.5f - d) * inv);
+    const float clast = phi_lower_f32(((float)(H + 1) - 0.5f - d) * inv);
     const float f = scale / ((1.0f - c0) - clast);
     const int m0 = max(0, -off), m1 = min(2 * H, NL - 1 - off);
     *plo = off + m0;
     *phi_ = off + m1;
     if (m0 > m1) return;
-    float cprev = c0;
-    bool pprev = false;  // the first edge lies left of the centre
-    if (m0 > 0) {
-        const float e = ((float)(m0 - H) - 0.5f - d) * inv;
-        cprev = normal_tail<false>(e);
-        pprev = e >= 0.0f;
-    }
+    float eprev = ((float)(m0 - H) - 0.5f - d) * inv;
+    float cprev = m0 == 0 ? c0 : phi_lower_f32(eprev);
     for (int m = m0; m <= m1; ++m) {
         const float e = ((float)(m + 1 - H) - 0.5f - d) * inv;
-        const float c = m == 2 * H ? clast : normal_tail<false>(e);
-        const bool pos = e >= 0.0f;
-        float v;
-        if (pprev) v = cprev - c;
-        else if (!pos) v = c - cprev;
-        else v = (1.0f - cprev) - c;
-        v *= f;
-        const E h = (E)v;
-        const E l = (E)(v - (float)h);
+        const float c = phi_lower_f32(e);
+        // both edges right of the centre: c_m - c_{m+1}; both left:
+        // c_{m+1} - c_m; one on each side: (1 - c_m) - c_{m+1}
+        const bool right = eprev >= 0.0f, left = e < 0.0f;
+        const float pa = right ? cprev : (left ? c : 1.0f - cprev);
+        const float pb = right || !left ? c : cprev;
+        const float v = pa - pb;
+        const float w = v * f;
+        const E h = (E)w;
+        const E l = (E)(w - (float)h);
         const int a = lds_at(off + m, s);
         hi[a] = __builtin_bit_cast(unsigned short, h);
         lo[a] = __builtin_bit_cast(unsigned short, l);
         cprev = c;
-        pprev = pos;
+        eprev = e;
     }
 }
 

@@ -66,6 +66,40 @@ __device__ __forceinline__ float phi_tail_f32(float z)
     return 0.5f * t * __builtin_amdgcn_exp2f(fmaf(-x, x, p) * 1.4426950408889634f);
 }
 
+// Phi(-|z|) in FP32 from two fitted forms (coefficients: least-squares fits
+// to the exact function, made by fit_normal_tail.py beside this file):
+//   |z| < 1:  1/2 - |z| Q(z^2), Q of degree 5 (the odd series of the CDF);
+//   |z| >= 1: exp(-z^2 / 2) S(1 / (1 + 0.35 |z|)), S of degree 9, fitted in
+//             relative error up to |z| = 9.
+// Absolute error below 1e-7 over the whole range (about one FP32 ulp of
+// 1/2, as erfcf), in 24 instructions without branches.
+__device__ __forceinline__ float phi_lower_f32(float z)
+{
+    const float x = fabsf(z);
+    const float u = x * x;
+    float q = -7.661413292e-06f;
+    q = fmaf(q, u, 1.134861668e-04f);
+    q = fmaf(q, u, -1.186309266e-03f);
+    q = fmaf(q, u, 9.973305278e-03f);
+    q = fmaf(q, u, -6.649035215e-02f);
+    q = fmaf(q, u, 3.989422917e-01f);
+    const float centre = fmaf(-x, q, 0.5f);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.35f, x, 1.0f));
+    float p = -3.970254585e-02f;
+    p = fmaf(p, t, 1.906433702e-01f);
+    p = fmaf(p, t, -3.446725309e-01f);
+    p = fmaf(p, t, 2.548686564e-01f);
+    p = fmaf(p, t, -8.698244393e-02f);
+    p = fmaf(p, t, 1.328877807e-01f);
+    p = fmaf(p, t, 1.123037711e-01f);
+    p = fmaf(p, t, 1.411426216e-01f);
+    p = fmaf(p, t, 1.394989341e-01f);
+    p = fmaf(p, t, 5.031029559e-06f);
+    // exp(-u / 2) = 2^(-u / (2 ln 2))
+    const float tail = __builtin_amdgcn_exp2f(u * -0.7213475204f) * p;
+    return x < 1.0f ? centre : tail;
+}
+
 // Phi(-|e|): library erfcf, or the FP32 fitted tail when FAST.
 template <bool FAST>
 __device__ __forceinline__ float normal_tail(float e)
