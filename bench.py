@@ -532,6 +532,9 @@ def main():
                     help="skip the separable / noise / HIRES-shaped measurements")
     ap.add_argument("--profile-once", action="store_true",
                     help="one batch launch of the timed configuration, then exit (for counters)")
+    ap.add_argument("--profile-sep", default="", metavar="PREC",
+                    help="two C2 separable renders at PREC (f64, f32, f16_hilo, bf16_hilo), "
+                         "then exit (for counters)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one device copy of MIB MiB and exit (HBM counter calibration)")
     args = ap.parse_args()
@@ -555,6 +558,22 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         log(f"copied {args.copy_calibration} MiB")
+        return
+    if args.profile_sep:
+        c2 = scene("c2")
+        ctx = E.e2e_create(0, 0)
+        ld2 = P.Loaded(ctx, c2)
+        sp2 = [torch.from_numpy(s).to("cuda") for s in c2.spectra]
+        out2 = torch.empty((c2.ny, c2.nx), dtype=torch.float32, device="cuda")
+        r, k = P.make_req(ld2, [s.data_ptr() for s in sp2], E.E2E_F32, out2.data_ptr(),
+                          E.E2E_F32, spectra_on_device=True, out_on_device=True, rv_mps=2.0,
+                          precision=args.profile_sep)
+        for _ in range(2):
+            E.e2e_render(ctx, r)
+        torch.cuda.synchronize()
+        log(f"two c2 renders at {args.profile_sep} done")
+        ld2.free()
+        E.e2e_destroy(ctx)
         return
     log("building c1 workload")
     sc = scene("c1")

@@ -108,15 +108,19 @@ def test_batch_equals_single_bitwise():
         ld.free()
 
 
-def test_separable_batch_equals_single_bitwise():
-    """The separable kernel's persistent (work-list) launch gives the same
-    bits as its plain launch, frame by frame, and matches the oracle."""
+@pytest.mark.parametrize("prec", ["f64", "f16_hilo"])
+def test_separable_batch_equals_single_bitwise(prec):
+    """The separable kernels' persistent (work-list) launch gives the same
+    bits as their plain launch, frame by frame, and matches the oracle: the
+    VALU kernel (f64) and the MFMA kernel (f16_hilo; c0's circular PSF takes
+    the VALU kernel at any precision)."""
     gu = _gu()
     from paper_2008_05858_amd import Loaded
     scs = [scene("mini_sep"), scene("mini_sep", seed=31), scene("c0")]
-    rqs = [Request(rv_mps=2.5, flux_scale=1.5), Request(rv_mps=-6.0), Request(rv_mps=0.4)]
+    rqs = [Request(rv_mps=2.5, flux_scale=1.5, precision=prec),
+           Request(rv_mps=-6.0, precision=prec), Request(rv_mps=0.4, precision=prec)]
     lds = [Loaded(gu.ctx(), s) for s in scs]
-    print("case separable batch of mini_sep x2 + c0", flush=True)
+    print(f"case separable batch of mini_sep x2 + c0, precision {prec}", flush=True)
     for grp in ((0, 1), (2,)):
         outs = gu.render_batch([scs[i] for i in grp], [rqs[i] for i in grp], [lds[i] for i in grp])
         for i, ob in zip(grp, outs):
