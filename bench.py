@@ -2,11 +2,26 @@
 
 A step renders a batch of B frames of the 9216 x 9216, 85-order x 2-fiber x
 2-slice, 1e6-samples-per-trace workload (11 x 11 field nodes of 32 x 32 x4
-tabulated PSFs) in one persistent launch through the C ABI, every frame
-with its own Doppler shift (U[-10, 10] m/s) and exposure scale.  Inputs are
-resident in HBM before the timed region.  Prints one JSON line.
+tabulated PSFs) in one persistent launch through the C ABI (a captured HIP
+graph: planner, counter reset, render), every frame with its own Doppler
+shift (U[-10, 10] m/s) and exposure scale.  Inputs are resident in HBM
+before the timed region.  Prints one JSON line with:
+
+* value: whole-job sample-PSF-pixel updates/s over the K timed steps;
+* roofline: render_table against the 78.6 TFLOP/s ALU peak, flops counted as
+  the deposit + stencil form (table_flops_frame), the kernel's time from HIP
+  events on its stream (eager launches); traffic from the committed
+  FETCH_SIZE / WRITE_SIZE summary while the kernel source is unchanged;
+* cpu_baseline: the FP64 oracle on the host's cores (OpenMP driver) and on
+  one core, on a bounded sample of the same frame;
+* accuracy: per-pixel error / peak at stratified pixels and photocentre
+  shifts (px and cm/s) of the timed frame, C2 at each precision and C3;
+* secondary: C2 precision variants, noise, detector stage, extraction + CCF,
+  aliasing sweep, C4, explicit SFIs, C3 (64 uneven frames in one launch);
+* serve: the served C0/C1/C4 mix at 20 req/s and a load sweep.
 
   python bench.py [--steps K] [--warmup W] [--batch B] [--gpus 1]
+  python bench.py --profile-once | --profile-sep PREC | --copy-calibration MIB
 """
 import argparse
 import json
