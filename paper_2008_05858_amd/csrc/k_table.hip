@@ -140,14 +140,27 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
     __shared__ int sh_qmin[2], sh_qmax[2];
     __shared__ unsigned sh_dmax[2];
 
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int l16 = lane & 15, lg = lane >> 4;
+    // The thread index is re-read through an empty asm statement (which the
+    // compiler cannot see through) at the top of each loop level, so the
+    // addresses, masks and conversions derived from it are recomputed where
+    // they are used instead of being hoisted to the kernel entry and held, or
+    // spilled, across the whole kernel; the same for the segment's sample range
+    // in each node-cell pass.  (This removed every VGPR spill at 3 workgroups
+    // per CU.)
+    const int tid_in = threadIdx.x;
+    auto fresh_tid = [&]() {
+        int t = tid_in;
+        asm volatile("" : "+v"(t));
+        return t;
+    };
+    const int tid = fresh_tid();
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (tid == 0) sh_touch = 0;
     int cpar = 0;  // parity of the node-cell pass
 
     for (int iter = 0;; ++iter) {
+        const int tid = fresh_tid();
+        const int lane = tid & 63;
         int fi, unit;
         if (work == nullptr) {
             if (iter > 0) break;
@@ -226,6 +239,8 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
         }
 
         for (int ty = ty_a; ty < ty_b; ++ty) {
+        const int tid = fresh_tid();
+        const int lane = tid & 63;
         const int Y0 = ty * TH;
         const int up = (ty - ty_a) & 1;  // unfinished list of the tile above
         const int nup = uniform_i(sh_nunf[up]);
@@ -309,7 +324,6 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 raw.w = uniform_i(raw.w);
                 __builtin_memcpy(&sg, &raw, sizeof(sg));
             }
-            const int k0 = sg.k0, k1 = sg.k1;
             const bool multi = (sg.cx0 != sg.cx1) | (sg.cy0 != sg.cy1);
             // output rows this pass owns: from the tile top (or below the rows
             // the tile above already carried) to the end of the carry
@@ -318,6 +332,10 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
 
             for (int cyc = sg.cy0; cyc <= sg.cy1; ++cyc)
             for (int cxc = sg.cx0; cxc <= sg.cx1; ++cxc) {
+                const int tid = fresh_tid();
+                const int lane = tid & 63;
+                int k0 = sg.k0, k1 = sg.k1;
+                asm volatile("" : "+s"(k0), "+s"(k1));
                 cpar ^= 1;
                 cptr<TraceDev> Tp = as_const(Fp->tr) + tr;
                 double cxr[DX + 1], cyr[DY + 1];
@@ -689,6 +707,9 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 gptr<h8> tfr = as_global(reinterpret_cast<const h8 *>(Fp->tfrag)) +
                                (size_t)(my * gxn + mx) * (2 * 4 * NFR * FRS / 8);
                 for (int A = rlo; A <= rhi; A += 4) {
+                    const int tid = fresh_tid();
+                    const int lane = tid & 63;
+                    const int l16 = lane & 15, lg = lane >> 4;
                     const int C = A & 3;
                     // 3a. slot c's deposits in band rows A..A+3, scaled, as fp16
                     // hi + lo parts
