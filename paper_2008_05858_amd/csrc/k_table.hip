@@ -135,6 +135,7 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
     __shared__ TraceFrameDev cmeta[KC];          // per-frame constants
     __shared__ unsigned char tlist[KC];          // this tile's items (candidate index)
     __shared__ int sh_wsum[4], sh_item, sh_touch;
+    __shared__ int sh_tsum[2][4];                // tile item counts per wave, by tile parity
     // per node-cell pass reductions, double-buffered by pass parity so a
     // pass's reset cannot meet a slow wave's read of the previous pass
     __shared__ int sh_qmin[2], sh_qmax[2];
@@ -269,13 +270,15 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 ok = reach && (fresh || more);
                 cnt_c = ok && !fresh;
             }
+            // (the counts alternate between two buffers: a wave may reach the
+            // next tile's count while another still reads this one's)
             const unsigned long long m = __ballot(ok);
-            if (lane == 0) sh_wsum[wv] = __popcll(m);
+            if (lane == 0) sh_tsum[up][wv] = __popcll(m);
             __syncthreads();
             int pos = __popcll(m & ((1ull << lane) - 1ull)), tot = 0;
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
-                const int v = sh_wsum[w];
+                const int v = sh_tsum[up][w];
                 pos += w < wv ? v : 0;
                 tot += v;
             }
@@ -284,6 +287,26 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 tcont[pos] = cnt_c;
             }
             count = uniform_i(tot);
+        }
+        if (count == 0) {
+            // no item: the tile is the rows carried down from the tile above,
+            // written at once (each thread clears the carry entries it reads)
+            for (int e = tid; e < TH * TW; e += kTableThreads) {
+                const int r = e / TW, c = e % TW;
+                double v = 0.0;
+                if (r < CR) {
+                    v = carry[r][c];
+                    carry[r][c] = 0.0;
+                }
+                const int gx = X0 + c, gy = Y0 + r;
+                if (gx < Fp->nx && gy < Fp->ny) {
+                    const size_t o = (size_t)gy * Fp->nx + gx;
+                    if (Fp->out_f64) ((double *)Fp->out)[o] = v;
+                    else ((float *)Fp->out)[o] = (float)v;
+                }
+            }
+            if (tid == 0) sh_nunf[up ^ 1] = 0;
+            continue;
         }
         // the tile starts from the rows carried down from the tile above
         for (int e = tid; e < TH * TW; e += kTableThreads) {
@@ -543,7 +566,9 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 auto sample = [&](double sv, auto mc) {
                     double rx = px[0];
                     double ry = py[0];
-                    if (ry < 0.0 || ry >= 1.0) {  // the row changes (rare)
+                    // the row changes (rare) unless 0 <= ry < 1: one unsigned
+                    // compare of the high word (negative values have the sign bit)
+                    if ((unsigned)(__double_as_longlong(ry) >> 32) >= 0x3ff00000u) {
                         flush();
 #pragma unroll
                         for (int a = 0; a < 3; ++a)
@@ -810,7 +835,8 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 else ((float *)Fp->out)[o] = (float)tile[r][c];
             }
         }
-        __syncthreads();
+        // (no barrier: the next tile writes the tile array only after its
+        // count barrier, which every wave reaches after this write-out)
         }  // tiles of the unit
     }
 }
