@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
     __shared__ SegDev cseg[KC];                  // segment record,
     __shared__ TraceFrameDev cmeta[KC];          // per-frame constants
     __shared__ unsigned char tlist[KC];          // this tile's items (candidate index)
-    __shared__ int sh_wsum[4], sh_item, sh_touch;
+    __shared__ int sh_wsum[4], sh_item;
     __shared__ int sh_tsum[2][4];                // tile item counts per wave, by tile parity
     // per node-cell pass reductions, double-buffered by pass parity so a
     // pass's reset cannot meet a slow wave's read of the previous pass
@@ -156,7 +156,6 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
     };
     const int tid = fresh_tid();
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    if (tid == 0) sh_touch = 0;
     int cpar = 0;  // parity of the node-cell pass
 
     for (int iter = 0;; ++iter) {
@@ -321,19 +320,6 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
         if (tid == 0) sh_nunf[up ^ 1] = 0;
         __syncthreads();
         const bool last_tile = ty + 1 >= ty_b;
-        // Spectrum prefetch, one item ahead: item 0's range now, item i+1's
-        // after item i's sample pass.  Vector loads complete in order, so a
-        // prefetch must follow the loads that are needed before it; the sum
-        // is only consumed at the end of the tile.
-        float touch = 0.0f;
-        auto prefetch = [&](int li) {
-            const int c = uniform_i(tlist[li]);
-            gptr<ST> sp = as_global(uniform_ptr<ST>(cmeta[c].spec));
-            const int a = uniform_i(cseg[c].k0), b = uniform_i(cseg[c].k1);
-            for (int kk = a + 32 * tid; kk < b; kk += 32 * kTableThreads)
-                touch += (float)spec_at(sp, kk);
-        };
-        if (count > 0) prefetch(0);
 
         for (int li = 0; li < count; ++li) {
             const int ci = uniform_i(tlist[li]);
@@ -399,13 +385,19 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                     if (guard >= 256) atomicOr(err, kErrSearch);
                     return k;
                 };
-                kst[tid] = search(q);
+                const int ks_own = search(q);
+                kst[tid] = ks_own;
                 if (tid == NCOL - 1) kst[NCOL] = search(q + 1);
                 if (tid == 0) {
                     sh_qmin[cpar] = 0x7fffffff;
                     sh_qmax[cpar] = -0x7fffffff;
                     sh_dmax[cpar] = 0u;
                 }
+                // the column's first spectrum values, loaded before the barrier
+                // so that their latency overlaps it
+                constexpr int G = SpecVec<ST>::G;
+                ST v0[G];
+                SpecVec<ST>::load(spec, ks_own, nspec, v0);
                 __syncthreads();
 
                 // ---- 2. this column's samples, in order.  Within one row run the
@@ -611,9 +603,9 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                     setup();
                     // spectrum values G at a time (one 16-byte load per lane),
                     // the next group's load issued before this group's samples
-                    constexpr int G = SpecVec<ST>::G;
                     ST v[G], nv[G];
-                    SpecVec<ST>::load(spec, ks, nspec, v);
+#pragma unroll
+                    for (int e = 0; e < G; ++e) v[e] = v0[e];
                     for (int kb = ks; kb < ke; kb += G) {
                         SpecVec<ST>::load(spec, min(kb + G, ke - 1), nspec, nv);
 #pragma unroll
@@ -626,7 +618,6 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 };
                 if (multi) walk(std::true_type());
                 else walk(std::false_type());
-                if (cyc == sg.cy1 && cxc == sg.cx1 && li + 1 < count) prefetch(li + 1);
                 // the left-slot halves belong to slot c - 1: hand them (and the
                 // window's first row) to the column on the left through LDS
                 float *xw = reinterpret_cast<float *>(bandbuf);
@@ -736,6 +727,12 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                     const int lane = tid & 63;
                     const int l16 = lane & 15, lg = lane >> 4;
                     const int C = A & 3;
+                    // this wave's first tap fragments (both planes) of the band's
+                    // phase, issued before the band is written and the barrier
+                    const int row = min(l16, NJ);
+                    gptr<h8> fh = tfr + ((size_t)(0 * 4 + C) * NFR + row) * (FRS / 8) + lg;
+                    gptr<h8> fl = tfr + ((size_t)(1 * 4 + C) * NFR + row) * (FRS / 8) + lg;
+                    h8 bh = fh[0], bl = fl[0];
                     // 3a. slot c's deposits in band rows A..A+3, scaled, as fp16
                     // hi + lo parts
                     {
@@ -764,15 +761,11 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                     // of the band phase (loaded one k-step ahead).
                     f4 acc[4];
                     {
-                        const int row = min(l16, NJ);
-                        gptr<h8> fh = tfr + ((size_t)(0 * 4 + C) * NFR + row) * (FRS / 8) + lg;
-                        gptr<h8> fl = tfr + ((size_t)(1 * 4 + C) * NFR + row) * (FRS / 8) + lg;
                         // this lane's band row: slot 4 l16 + 2 lg of layer wv, plane 0
                         const h8 *ap = reinterpret_cast<const h8 *>(bandbuf) +
                                        ((wv * RL + 4 * l16 + 2 * lg) >> 1);
 #pragma unroll
                         for (int mb = 0; mb < 4; ++mb) acc[mb] = f4{0.f, 0.f, 0.f, 0.f};
-                        h8 bh = fh[0], bl = fl[0];
 #pragma unroll
                         for (int t = 0; t < NKS; ++t) {
                             h8 nh = bh, nl = bl;
@@ -822,7 +815,6 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 }
             }
         }
-        if (touch == -1.0f) sh_touch = 1;  // keeps the prefetch loads
         __syncthreads();
 
         // ---- write the tile once
