@@ -244,6 +244,11 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
         const int Y0 = ty * TH;
         const int up = (ty - ty_a) & 1;  // unfinished list of the tile above
         const int nup = uniform_i(sh_nunf[up]);
+        // this tile's own list starts empty.  Reset here, before the count
+        // barrier: the list was last read in the previous tile's selection,
+        // which every wave has left, and the reset is visible to all after
+        // the barrier, including to the next tile when this one has no item.
+        if (tid == 0) sh_nunf[up ^ 1] = 0;
 
         // ---- this tile's items, ascending: thread c tests candidate c.  A
         // segment is taken at the first tile of the run it reaches, and again
@@ -304,7 +309,6 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                     else ((float *)Fp->out)[o] = (float)v;
                 }
             }
-            if (tid == 0) sh_nunf[up ^ 1] = 0;
             continue;
         }
         // the tile starts from the rows carried down from the tile above
@@ -317,7 +321,6 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 tile[r][c] = 0.0;
             }
         }
-        if (tid == 0) sh_nunf[up ^ 1] = 0;
         __syncthreads();
         const bool last_tile = ty + 1 >= ty_b;
 
@@ -812,6 +815,10 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                             }
                         }
                     }
+                    // the next band is written over the partials: every wave must
+                    // have read its own first (after the last band, the next write
+                    // to this buffer follows the next pass's search barrier)
+                    if (A + 4 <= rhi) __syncthreads();
                 }
             }
         }
