@@ -714,11 +714,16 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 __syncthreads();  // the exchange area becomes the band
                 // rows A - mrb .. A - mrb + 3 of the packed window (zero outside):
                 // with o = A - mrb + 3, halfs o..o+3 of [0, 0, 0, row 0 .. row 4, 0 ...]
+                // (a 128-bit funnel shift, without branches: the columns of a wave
+                // have different o)
                 auto band4 = [](unsigned w0, unsigned long long w1, int o) -> unsigned long long {
-                    if (o < 0 || o > 7) return 0ull;
-                    if (o >= 4) return w1 >> (16 * (o - 4));
-                    const unsigned long long w0x = (unsigned long long)w0 << 32;
-                    return o == 0 ? w0x : (w0x >> (16 * o)) | (w1 << (64 - 16 * o));
+                    const unsigned long long lo = (unsigned long long)w0 << 32;
+                    const unsigned sh = 16u * (unsigned)o;
+                    const unsigned long long a = lo >> (sh & 63u);
+                    const unsigned long long b = w1 << ((64u - sh) & 63u);
+                    const unsigned long long c = w1 >> ((sh - 64u) & 63u);
+                    const unsigned long long r = sh >= 64u ? c : (sh == 0u ? a : (a | b));
+                    return (o < 0 || o > 7) ? 0ull : r;
                 };
                 // this wave's node layer: fragments of its taps (both planes)
                 const int mx = min(nbx + (wv & 1), gxn - 1);
