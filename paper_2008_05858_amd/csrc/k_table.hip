@@ -94,7 +94,7 @@ struct SpecVec<double> {
 };
 
 template <int KW, int DX, int DY, typename ST>
-__global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_table(
+__global__ __launch_bounds__(kTableThreads, 3) void k_render_table(
     const FrameDev *__restrict__ frames, const int2 *__restrict__ work, int n_work,
     int *__restrict__ counter, int *__restrict__ err)
 {
@@ -132,7 +132,10 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
     __shared__ int kst[NCOL + 1];
     __shared__ int ctr[KC];                      // the run's trace segments: trace,
     __shared__ SegDev cseg[KC];                  // segment record,
-    __shared__ TraceFrameDev cmeta[KC];          // per-frame constants
+    // per-frame constants of the run's segments (kept in LDS for 32-cell
+    // tables; 48-cell tables read them from memory, so 3 workgroups fit a CU)
+    constexpr bool kMetaLds = KW <= 32;
+    __shared__ TraceFrameDev cmeta[kMetaLds ? KC : 1];
     __shared__ unsigned char tlist[KC];          // this tile's items (candidate index)
     __shared__ int sh_wsum[4], sh_item;
     __shared__ int sh_tsum[2][4];                // tile item counts per wave, by tile parity
@@ -228,7 +231,7 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
                 if (pos < KC) {
                     ctr[pos] = mb + j;
                     cseg[pos] = sgv[j];
-                    cmeta[pos] = Fp->tf[mb + j];
+                    if constexpr (kMetaLds) cmeta[pos] = Fp->tf[mb + j];
                 } else {
                     atomicOr(err, kErrTileTraces);
                 }
@@ -356,9 +359,20 @@ __global__ __launch_bounds__(kTableThreads, KW <= 32 ? 3 : 2) void k_render_tabl
 #pragma unroll
                 for (int j = 0; j <= DY; ++j) cyr[j] = Tp->cy[j];
                 const int nspec = Tp->n;
-                const double t0 = uniform_d(cmeta[ci].t0), dt = uniform_d(cmeta[ci].dt);
-                const double scale = uniform_d(cmeta[ci].scale);
-                gptr<ST> spec = as_global(uniform_ptr<ST>(cmeta[ci].spec));
+                double t0, dt, scale;
+                gptr<ST> spec;
+                if constexpr (kMetaLds) {
+                    t0 = uniform_d(cmeta[ci].t0);
+                    dt = uniform_d(cmeta[ci].dt);
+                    scale = uniform_d(cmeta[ci].scale);
+                    spec = as_global(uniform_ptr<ST>(cmeta[ci].spec));
+                } else {
+                    cptr<TraceFrameDev> Mp = as_const(Fp->tf) + tr;
+                    t0 = Mp->t0;
+                    dt = Mp->dt;
+                    scale = Mp->scale;
+                    spec = as_global(reinterpret_cast<const ST *>(Mp->spec));
+                }
                 const double gsx = Fp->gsx, gsy = Fp->gsy;
                 const int gxn = Fp->gx, gyn = Fp->gy;
                 const double ua = fma(horner<DX>(cxr, fma((double)k0, dt, t0)), (double)OS, UC);
@@ -873,7 +887,7 @@ hipError_t launch_deg(const FrameDev *frames_dev, int degx, int degy, int spec_f
 hipError_t launch_table(const FrameDev *frames_dev, const KernelCfg &cfg, const int2 *work,
                         int n_work, int *counter, int *err, hipStream_t s)
 {
-    const int fit = cfg.kw <= 32 ? 3 : 2;  // workgroups per CU the kernel's resources allow
+    const int fit = 3;  // workgroups per CU the kernel's resources allow
     const int resident = cfg.resident > 0 && cfg.resident < fit ? cfg.resident : fit;
     const int cap = 256 * resident;
     int nblocks = work == nullptr ? cfg.plain_tiles : (n_work < cap ? n_work : cap);
