@@ -9,32 +9,24 @@ namespace e2e {
 
 namespace {
 
-__device__ double x_at(const TraceDev &T, double t0, double dt, int k)
+// The coefficients are held in registers, padded with zeros to degree 7
+// (the format loader zeroes them; a zero leading coefficient leaves Horner's
+// value bit-identical), so the bisection steps do not reload them.
+__device__ double x_at(const double *cx, double t0, double dt, int k)
 {
-    double t = fma((double)k, dt, t0);
-    double v = T.cx[T.degx];
-    for (int j = T.degx - 1; j >= 0; --j) v = fma(v, t, T.cx[j]);
-    return v;
-}
-
-__device__ double y_at_t(const TraceDev &T, double t)
-{
-    double v = T.cy[T.degy];
-    for (int j = T.degy - 1; j >= 0; --j) v = fma(v, t, T.cy[j]);
-    return v;
+    return horner<kNCoef - 1>(cx, fma((double)k, dt, t0));
 }
 
 // first k in [lo, hi] with x(k) >= xv (hi if none)
-__device__ int first_at_or_above(const TraceDev &T, double t0, double dt, double xv, int lo,
+__device__ int first_at_or_above(const double *cx, double t0, double dt, double xv, int lo,
                                  int hi)
 {
     while (lo < hi) {
         int mid = lo + (hi - lo) / 2;
-        if (x_at(T, t0, dt, mid) >= xv) hi = mid; else lo = mid + 1;
+        if (x_at(cx, t0, dt, mid) >= xv) hi = mid; else lo = mid + 1;
     }
     return lo;
 }
-
 
 __global__ void k_plan(const FrameDev *__restrict__ frames, int *__restrict__ err)
 {
@@ -49,6 +41,12 @@ __global__ void k_plan(const FrameDev *__restrict__ frames, int *__restrict__ er
 
     double t0, dt;
     trace_affine(T, F.beta, &t0, &dt);
+    double cx[kNCoef], cy[kNCoef];
+#pragma unroll
+    for (int j = 0; j < kNCoef; ++j) {
+        cx[j] = T.cx[j];
+        cy[j] = T.cy[j];
+    }
     if (c == 0) {
         TraceFrameDev tfd;
         tfd.t0 = t0;
@@ -70,8 +68,8 @@ __global__ void k_plan(const FrameDev *__restrict__ frames, int *__restrict__ er
     }
     xlo -= 1e-3;
     xhi += 1e-3;
-    int k0 = first_at_or_above(T, t0, dt, xlo, 0, T.n);
-    int k1 = first_at_or_above(T, t0, dt, xhi, k0, T.n);
+    int k0 = first_at_or_above(cx, t0, dt, xlo, 0, T.n);
+    int k1 = first_at_or_above(cx, t0, dt, xhi, k0, T.n);
     if (k0 < k1) {
         // y range over [k0, k1): 9 nodes plus the curvature bound between them
         const int NP = 9;
@@ -79,7 +77,7 @@ __global__ void k_plan(const FrameDev *__restrict__ frames, int *__restrict__ er
         double ymin = 1e300, ymax = -1e300;
         for (int q = 0; q < NP; ++q) {
             double t = (q == NP - 1) ? tb : ta + (tb - ta) * (double)q / (NP - 1);
-            double y = y_at_t(T, t);
+            double y = horner<kNCoef - 1>(cy, t);
             ymin = fmin(ymin, y);
             ymax = fmax(ymax, y);
         }
@@ -103,8 +101,8 @@ __global__ void k_plan(const FrameDev *__restrict__ frames, int *__restrict__ er
             S.ty0 = (int16_t)ty0;
             S.ty1 = (int16_t)ty1;
             if (table) {
-                int ca = ext_cell(x_at(T, t0, dt, k0), F.gsx, F.gx);
-                int cb = ext_cell(x_at(T, t0, dt, k1 - 1), F.gsx, F.gx);
+                int ca = ext_cell(x_at(cx, t0, dt, k0), F.gsx, F.gx);
+                int cb = ext_cell(x_at(cx, t0, dt, k1 - 1), F.gsx, F.gx);
                 int ra = ext_cell(ymin, F.gsy, F.gy);
                 int rb = ext_cell(ymax, F.gsy, F.gy);
                 S.cx0 = (int8_t)ca;
