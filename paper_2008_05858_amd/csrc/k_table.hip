@@ -623,14 +623,17 @@ __global__ __launch_bounds__(kTableThreads, 3) void k_render_table(
                     ST v[G], nv[G];
 #pragma unroll
                     for (int e = 0; e < G; ++e) v[e] = v0[e];
-                    for (int kb = ks; kb < ke; kb += G) {
+                    int kb = ks;
+                    for (; kb + G <= ke; kb += G) {  // whole groups: no per-sample test
                         SpecVec<ST>::load(spec, min(kb + G, ke - 1), nspec, nv);
 #pragma unroll
-                        for (int e = 0; e < G; ++e)
-                            if (kb + e < ke) sample((double)v[e], mc);
+                        for (int e = 0; e < G; ++e) sample((double)v[e], mc);
 #pragma unroll
                         for (int e = 0; e < G; ++e) v[e] = nv[e];
                     }
+#pragma unroll
+                    for (int e = 0; e < G - 1; ++e)
+                        if (kb + e < ke) sample((double)v[e], mc);
                     flush();
                 };
                 if (multi) walk(std::true_type());
