@@ -375,30 +375,42 @@ __global__ __launch_bounds__(kTableThreads, 3) void k_render_table(
                 }
                 const double gsx = Fp->gsx, gsy = Fp->gsy;
                 const int gxn = Fp->gx, gyn = Fp->gy;
-                const double ua = fma(horner<DX>(cxr, fma((double)k0, dt, t0)), (double)OS, UC);
-                const double ub = fma(horner<DX>(cxr, fma((double)(k1 - 1), dt, t0)), (double)OS, UC);
-                const double inv_slope = ub > ua ? (double)(k1 - 1 - k0) / (ub - ua) : 0.0;
-
                 // ---- 1. samples of each slot column: first k with u(k) >= q
                 const int q = OS * X0 - KW + tid;
                 auto u_of = [&](int k) {
                     double x = horner<DX>(cxr, fma((double)k, dt, t0));
                     return fma(x, (double)OS, UC);
                 };
+                // The sample index as a function of the slot coordinate,
+                // interpolated (Newton form) through the segment's first,
+                // middle and last samples: a guess within a small fraction of
+                // a sample, which the exact test below settles.
+                const int km = k0 + ((k1 - 1 - k0) >> 1);
+                const double ua = u_of(k0), um = u_of(km), ub = u_of(k1 - 1);
+                double d1 = 0.0, d2 = 0.0;
+                if (km > k0 && km < k1 - 1) {  // three distinct samples (u grows with k)
+                    d1 = (double)(km - k0) / (um - ua);
+                    d2 = ((double)(k1 - 1 - km) / (ub - um) - d1) / (ub - ua);
+                }
                 auto search = [&](int qq) -> int {
-                    if ((double)qq <= ua) return k0;
-                    if ((double)qq > ub) return k1;
-                    // secant steps on the (nearly linear) slot index, then exact fix-up
-                    double kk = (double)k0 + ((double)qq - ua) * inv_slope;
-                    for (int it = 0; it < 2; ++it) {
-                        kk = fmin(fmax(kk, (double)k0), (double)(k1 - 1));
-                        kk -= (u_of((int)kk) - (double)qq) * inv_slope;
-                    }
+                    const double uq = (double)qq;
+                    if (uq <= ua) return k0;
+                    if (uq > ub) return k1;
+                    // here u(k0) < qq <= u(k1 - 1): the answer lies in [k0 + 1, k1 - 1]
+                    const double kk = fma((uq - ua), fma(uq - um, d2, d1), (double)k0);
                     int k = (int)ceil(fmin(fmax(kk, (double)k0), (double)(k1 - 1)));
                     k = min(max(k, k0 + 1), k1 - 1);
+                    // the guess and its left neighbour tested together; a miss
+                    // walks on (u(k0) < qq <= u(k1 - 1) ends either walk)
+                    const double uk = u_of(k), ul = u_of(k - 1);
                     int guard = 0;
-                    while (k < k1 && u_of(k) < (double)qq && guard < 256) { ++k; ++guard; }
-                    while (k > k0 && u_of(k - 1) >= (double)qq && guard < 256) { --k; ++guard; }
+                    if (uk < uq) {
+                        ++k;
+                        while (k < k1 - 1 && u_of(k) < uq && guard < 256) { ++k; ++guard; }
+                    } else if (ul >= uq) {
+                        --k;
+                        while (k > k0 + 1 && u_of(k - 1) >= uq && guard < 256) { --k; ++guard; }
+                    }
                     if (guard >= 256) atomicOr(err, kErrSearch);
                     return k;
                 };
