@@ -17,6 +17,18 @@ __device__ double x_at(const double *cx, double t0, double dt, int k)
     return horner<kNCoef - 1>(cx, fma((double)k, dt, t0));
 }
 
+// first k in [lo, hi] with u(k) = fma(x(k), os, uc) >= qv (hi if none): the
+// table path's slot coordinate, compared exactly as its render kernel does
+__device__ int first_slot_at_or_above(const double *cx, double t0, double dt, double os,
+                                      double uc, double qv, int lo, int hi)
+{
+    while (lo < hi) {
+        int mid = lo + (hi - lo) / 2;
+        if (fma(x_at(cx, t0, dt, mid), os, uc) >= qv) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
 // first k in [lo, hi] with x(k) >= xv (hi if none)
 __device__ int first_at_or_above(const double *cx, double t0, double dt, double xv, int lo,
                                  int hi)
@@ -66,10 +78,23 @@ __global__ void k_plan(const FrameDev *__restrict__ frames, int *__restrict__ er
         xlo = X0 - F.H - 0.5;
         xhi = X1 + F.H - 0.5;
     }
-    xlo -= 1e-3;
-    xhi += 1e-3;
-    int k0 = first_at_or_above(cx, t0, dt, xlo, 0, T.n);
-    int k1 = first_at_or_above(cx, t0, dt, xhi, k0, T.n);
+    int k0, k1;
+    if (table) {
+        // The render kernel's slot columns start at slot os X0 - kw (its left
+        // halo) and the tile's pixels end at slot os X1; its samples are those
+        // with u = os x + (os - kw)/2 in that range, found here with the
+        // kernel's own comparison (the format polynomial is zero-padded to
+        // degree 7, which leaves its value bit-identical), so the kernel takes
+        // the range's ends from here without searching for them.
+        const double os = (double)kOS, uc = 0.5 * (double)(kOS - F.kw);
+        k0 = first_slot_at_or_above(cx, t0, dt, os, uc, (double)(kOS * X0 - F.kw), 0, T.n);
+        k1 = first_slot_at_or_above(cx, t0, dt, os, uc, (double)(kOS * X1), k0, T.n);
+    } else {
+        xlo -= 1e-3;
+        xhi += 1e-3;
+        k0 = first_at_or_above(cx, t0, dt, xlo, 0, T.n);
+        k1 = first_at_or_above(cx, t0, dt, xhi, k0, T.n);
+    }
     if (k0 < k1) {
         // y range over [k0, k1): 9 nodes plus the curvature bound between them
         const int NP = 9;

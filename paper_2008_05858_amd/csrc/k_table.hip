@@ -61,6 +61,19 @@ typedef unsigned short u4s __attribute__((ext_vector_type(4)));
 // four spectrum values (two for FP64), read at any 4-byte-aligned index
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+// four FP64 tile pixels, moved through LDS as two 16-byte halves
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ d4 ld4(const double *p)
+{
+    const d2 a = *reinterpret_cast<const d2 *>(p), b = *reinterpret_cast<const d2 *>(p + 2);
+    return d4{a.x, a.y, b.x, b.y};
+}
+__device__ __forceinline__ void st4(double *p, d4 v)
+{
+    *reinterpret_cast<d2 *>(p) = d2{v.x, v.y};
+    *reinterpret_cast<d2 *>(p + 2) = d2{v.z, v.w};
+}
 
 template <typename ST>
 struct SpecVec;
@@ -93,6 +106,22 @@ struct SpecVec<double> {
     }
 };
 
+// Reduction over the 64 lanes of a wave by DPP row operations (exchange
+// within quads, mirrors within half-rows and rows, then row broadcasts into
+// the last row), read back from lane 63 as a uniform value.  Every lane of
+// the wave must be active.
+template <typename Op>
+__device__ int wave_reduce(int v, int ident, Op op)
+{
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x140, 0xF, 0xF, false));  // row_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 template <int KW, int DX, int DY, typename ST>
 __global__ __launch_bounds__(kTableThreads, 3) void k_render_table(
     const FrameDev *__restrict__ frames, const int2 *__restrict__ work, int n_work,
@@ -124,8 +153,10 @@ __global__ __launch_bounds__(kTableThreads, 3) void k_render_table(
     // The band (fp16 hi and lo planes of the 4 layers' deposits) and, once
     // the products have read it, the four layers' FP32 partial outputs.
     __shared__ __attribute__((aligned(16))) unsigned char bandbuf[BUFB];
-    __shared__ double tile[TH][TW];
-    __shared__ double carry[CR][TW];             // rows of the next tile
+    __shared__ __attribute__((aligned(16))) double tile[TH][TW];
+    __shared__ __attribute__((aligned(16))) double carry[CR][TW];  // rows of the next tile
+    static_assert(TW % 4 == 0, "tile rows move as groups of four pixels");
+    constexpr int TQ = TW / 4;                   // four-pixel groups per tile row
     __shared__ int unf[2][kUnf];                 // traces with rows beyond the carry
     __shared__ int sh_nunf[2];
     __shared__ unsigned char tcont[KC];          // item continues from the tile above
@@ -191,6 +222,28 @@ __global__ __launch_bounds__(kTableThreads, 3) void k_render_table(
         const int ty_b = min(ty_a + chunk, Fp->nty);
         const int X0 = tx * TW;
         const SegDev *segs = Fp->segs + (size_t)tx * ntr;
+        // four consecutive pixels of the frame from (gy, gx), rounded once to
+        // FP32 (one 16-byte store when the rows are a multiple of four pixels
+        // on a 16-byte boundary: gx is a multiple of four), or kept in FP64
+        auto put4 = [&](int gy, int gx, d4 v) {
+            const int nx = Fp->nx;
+            if (gy >= Fp->ny || gx >= nx) return;
+            const size_t o = (size_t)gy * nx + gx;
+            if (Fp->out_f64) {
+                double *d = (double *)Fp->out + o;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (gx + e < nx) d[e] = v[e];
+            } else if (((nx & 3) | ((unsigned)(size_t)Fp->out & 15u)) == 0) {
+                *reinterpret_cast<f4 *>((float *)Fp->out + o) =
+                    f4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+            } else {
+                float *d = (float *)Fp->out + o;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (gx + e < nx) d[e] = (float)v[e];
+            }
+        };
         for (int e = tid; e < CR * TW; e += kTableThreads) carry[e / TW][e % TW] = 0.0;
         if (tid < 2) sh_nunf[tid] = 0;
 
@@ -298,31 +351,26 @@ __global__ __launch_bounds__(kTableThreads, 3) void k_render_table(
         if (count == 0) {
             // no item: the tile is the rows carried down from the tile above,
             // written at once (each thread clears the carry entries it reads)
-            for (int e = tid; e < TH * TW; e += kTableThreads) {
-                const int r = e / TW, c = e % TW;
-                double v = 0.0;
+            for (int e = tid; e < TH * TQ; e += kTableThreads) {
+                const int r = e / TQ, c = 4 * (e % TQ);
+                d4 v = {0.0, 0.0, 0.0, 0.0};
                 if (r < CR) {
-                    v = carry[r][c];
-                    carry[r][c] = 0.0;
+                    v = ld4(&carry[r][c]);
+                    st4(&carry[r][c], d4{0.0, 0.0, 0.0, 0.0});
                 }
-                const int gx = X0 + c, gy = Y0 + r;
-                if (gx < Fp->nx && gy < Fp->ny) {
-                    const size_t o = (size_t)gy * Fp->nx + gx;
-                    if (Fp->out_f64) ((double *)Fp->out)[o] = v;
-                    else ((float *)Fp->out)[o] = (float)v;
-                }
+                put4(Y0 + r, X0 + c, v);
             }
             continue;
         }
         // the tile starts from the rows carried down from the tile above
-        for (int e = tid; e < TH * TW; e += kTableThreads) {
-            const int r = e / TW, c = e % TW;
+        for (int e = tid; e < TH * TQ; e += kTableThreads) {
+            const int r = e / TQ, c = 4 * (e % TQ);
+            d4 v = {0.0, 0.0, 0.0, 0.0};
             if (r < CR) {
-                tile[r][c] = carry[r][c];
-                carry[r][c] = 0.0;
-            } else {
-                tile[r][c] = 0.0;
+                v = ld4(&carry[r][c]);
+                st4(&carry[r][c], d4{0.0, 0.0, 0.0, 0.0});
             }
+            st4(&tile[r][c], v);
         }
         __syncthreads();
         const bool last_tile = ty + 1 >= ty_b;
@@ -416,7 +464,9 @@ __global__ __launch_bounds__(kTableThreads, 3) void k_render_table(
                 };
                 const int ks_own = search(q);
                 kst[tid] = ks_own;
-                if (tid == NCOL - 1) kst[NCOL] = search(q + 1);
+                // the last column ends where the planner's range ends (the
+                // first sample at or past the tile's right edge, or past the frame's)
+                if (tid == NCOL - 1) kst[NCOL] = k1;
                 if (tid == 0) {
                     sh_qmin[cpar] = 0x7fffffff;
                     sh_qmax[cpar] = -0x7fffffff;
@@ -659,17 +709,16 @@ __global__ __launch_bounds__(kTableThreads, 3) void k_render_table(
                     for (int r = 0; r < 4; ++r) xw[tid * XS + l * 4 + r] = wr[l][0][r];
                 xw[tid * XS + 16] = __int_as_float(rb);
                 // column bound on any one deposit: all its photons
-                float cmax = (float)(csum * scale) * 1.0001f;
-#pragma unroll
-                for (int o = 32; o >= 1; o >>= 1) {
-                    qmin = min(qmin, __shfl_xor(qmin, o));
-                    qmax = max(qmax, __shfl_xor(qmax, o));
-                    cmax = fmaxf(cmax, __shfl_xor(cmax, o));
-                }
-                if (lane == 0 && qmin <= qmax) {
-                    atomicMin(&sh_qmin[cpar], qmin);
-                    atomicMax(&sh_qmax[cpar], qmax);
-                    atomicMax(&sh_dmax[cpar], __float_as_uint(cmax));
+                const float cmax = (float)(csum * scale) * 1.0001f;  // >= 0
+                const int wqmin = wave_reduce(qmin, 0x7fffffff, [](int a, int b) { return min(a, b); });
+                const int wqmax = wave_reduce(qmax, -0x7fffffff, [](int a, int b) { return max(a, b); });
+                const unsigned wcmax = (unsigned)wave_reduce(
+                    __float_as_int(cmax), 0,
+                    [](int a, int b) { return (int)max((unsigned)a, (unsigned)b); });
+                if (lane == 0 && wqmin <= wqmax) {
+                    atomicMin(&sh_qmin[cpar], wqmin);
+                    atomicMax(&sh_qmax[cpar], wqmax);
+                    atomicMax(&sh_dmax[cpar], wcmax);
                 }
                 __syncthreads();
 
@@ -859,14 +908,9 @@ __global__ __launch_bounds__(kTableThreads, 3) void k_render_table(
         __syncthreads();
 
         // ---- write the tile once
-        for (int e = tid; e < TH * TW; e += kTableThreads) {
-            int r = e / TW, c = e % TW;
-            int gx = X0 + c, gy = Y0 + r;
-            if (gx < Fp->nx && gy < Fp->ny) {
-                size_t o = (size_t)gy * Fp->nx + gx;
-                if (Fp->out_f64) ((double *)Fp->out)[o] = tile[r][c];
-                else ((float *)Fp->out)[o] = (float)tile[r][c];
-            }
+        for (int e = tid; e < TH * TQ; e += kTableThreads) {
+            const int r = e / TQ, c = 4 * (e % TQ);
+            put4(Y0 + r, X0 + c, ld4(&tile[r][c]));
         }
         // (no barrier: the next tile writes the tile array only after its
         // count barrier, which every wave reaches after this write-out)
