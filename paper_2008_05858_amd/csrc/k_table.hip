@@ -486,7 +486,8 @@ __global__ __launch_bounds__(kTableThreads, 3) void k_render_table(
                 // run keeps the 9 moments sum phi rx^a ry^b (FP64) and turns
                 // them into deposits when the row changes.  Deposits go to the
                 // column's 4-row window wr[layer][x-slot][row] (rows rb..rb+3).
-                const int ks = kst[tid], ke = kst[tid + 1];
+                const int ks = kst[tid];
+                int ke = kst[tid + 1];
                 int nbx, nby;
                 double ax0, ax1, ay0, ay1;
                 cell_line(cxc, gsx, gxn, &nbx, &ax0, &ax1);
@@ -698,7 +699,23 @@ __global__ __launch_bounds__(kTableThreads, 3) void k_render_table(
                         if (kb + e < ke) sample((double)v[e], mc);
                     flush();
                 };
-                if (multi) walk(std::true_type());
+                // A segment that spans several node cells is walked once per
+                // cell.  A column whose x range lies wholly outside this cell
+                // (with a margin far above rounding) has no sample in it and is
+                // skipped; one wholly inside it, on a segment within one y cell,
+                // needs no per-sample test.  Only the columns at a cell boundary
+                // take the tested walk, and a wave takes it only if one of its
+                // columns needs it.
+                bool tested = multi;
+                if (multi) {
+                    const double xl = ((double)q - UC) / OS - 1e-6;
+                    const double xh = ((double)q + 1.0 - UC) / OS + 1e-6;
+                    const int ca = ext_cell(xl, gsx, gxn), cb = ext_cell(xh, gsx, gxn);
+                    if (ca > cxc || cb < cxc) ke = ks;
+                    const bool inside = ca == cxc && cb == cxc && sg.cy0 == sg.cy1;
+                    tested = !__all(inside || ke <= ks);
+                }
+                if (tested) walk(std::true_type());
                 else walk(std::false_type());
                 // the left-slot halves belong to slot c - 1: hand them (and the
                 // window's first row) to the column on the left through LDS
@@ -885,17 +902,15 @@ __global__ __launch_bounds__(kTableThreads, 3) void k_render_table(
                         const f4 p2 = part[(2 * 4 + wv) * 64 + lane];
                         const f4 p3 = part[(3 * 4 + wv) * 64 + lane];
                         const int o = (A >> 2) + l16;  // output row
-                        if (l16 < NJ && o >= out_lo && o <= out_hi) {
+                        const int i0 = 16 * wv + 4 * lg;  // first of the lane's 4 pixel columns
+                        if (l16 < NJ && o >= out_lo && o <= out_hi && i0 < TW) {
+                            double *row = o < Y0 + TH ? &tile[o - Y0][i0] : &carry[o - Y0 - TH][i0];
+                            d4 t = ld4(row);
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) {
-                                const int i = 16 * wv + 4 * lg + e;  // pixel column
-                                if (i < TW) {
-                                    const double v = ((((double)p0[e] + (double)p1[e]) +
-                                                       (double)p2[e]) + (double)p3[e]) * unsc;
-                                    if (o < Y0 + TH) tile[o - Y0][i] += v;
-                                    else carry[o - Y0 - TH][i] += v;
-                                }
-                            }
+                            for (int e = 0; e < 4; ++e)
+                                t[e] += ((((double)p0[e] + (double)p1[e]) + (double)p2[e]) +
+                                         (double)p3[e]) * unsc;
+                            st4(row, t);
                         }
                     }
                     // the next band is written over the partials: every wave must
