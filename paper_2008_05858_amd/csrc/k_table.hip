@@ -445,12 +445,28 @@ __global__ __launch_bounds__(kTableThreads, 3) void k_render_table(
                     if (uq <= ua) return k0;
                     if (uq > ub) return k1;
                     // here u(k0) < qq <= u(k1 - 1): the answer lies in [k0 + 1, k1 - 1]
-                    const double kk = fma((uq - ua), fma(uq - um, d2, d1), (double)k0);
-                    int k = (int)ceil(fmin(fmax(kk, (double)k0), (double)(k1 - 1)));
-                    k = min(max(k, k0 + 1), k1 - 1);
-                    // the guess and its left neighbour tested together; a miss
-                    // walks on (u(k0) < qq <= u(k1 - 1) ends either walk)
-                    const double uk = u_of(k), ul = u_of(k - 1);
+                    auto first_at = [&](double kk) {  // ceil, kept in [k0 + 1, k1 - 1]
+                        const int k = (int)ceil(fmin(fmax(kk, (double)k0), (double)(k1 - 1)));
+                        return min(max(k, k0 + 1), k1 - 1);
+                    };
+                    int k = first_at(fma((uq - ua), fma(uq - um, d2, d1), (double)k0));
+                    // the guess and its left neighbour tested together
+                    double uk = u_of(k), ul = u_of(k - 1);
+                    // A guess more than a sample off (densely sampled segments
+                    // whose format bends over the segment): secant steps on the
+                    // slope between the two evaluated samples.
+                    for (int it = 0; it < 8 && (uk < uq || ul >= uq); ++it) {
+                        const double du = uk - ul;
+                        if (!(du > 0.0)) break;
+                        int kn = first_at((double)k + (uq - uk) / du);
+                        if (kn == k) kn = uk < uq ? min(k + 1, k1 - 1) : max(k - 1, k0 + 1);
+                        if (kn == k) break;
+                        k = kn;
+                        uk = u_of(k);
+                        ul = u_of(k - 1);
+                    }
+                    // a remaining miss walks on (u(k0) < qq <= u(k1 - 1) ends
+                    // either walk)
                     int guard = 0;
                     if (uk < uq) {
                         ++k;

@@ -59,6 +59,22 @@ def test_c1_batch_sampled():
     ld.free()
 
 
+def test_dense_sampling_table():
+    """Densely sampled traces: 2e7 samples per trace over ~480 px, about 1e4
+    per quarter-pixel slot column, where the table path's first guess of a
+    column's first sample (an inverse quadratic over the tile's segment) can be
+    hundreds of samples off.  The render must find every column's samples
+    exactly (no device error) and match the oracle; 16 sampled pixels keep the
+    oracle's per-pixel gather (about 1 s per pixel here) short."""
+    gu = _gu()
+    sc = scene("mini_table", n_samp=20_000_000)
+    rq = Request(rv_mps=39.0)
+    print("case mini_table with 2e7 samples per trace", flush=True)
+    g = gu.render(sc, rq)
+    err = _check("mini_table dense", sc, rq, g, n_bright=12, n_rand=4, seed=3)
+    assert err < TOL
+
+
 def _strat_check(name, sc, rq, g, tw=56, th=32, n_each=25, seed=0):
     """Parity at stratified pixels: tile-boundary and carry rows, tile-column
     edges, node-cell boundary lines, bright pixels, trace ends, anywhere."""
