@@ -793,8 +793,16 @@ e2e_status e2e::run_frames(e2e_ctx *ctx, const e2e_render_req *reqs, int n, bool
         std::stable_sort(order.begin(), order.end(),
                          [&](int a, int b) { return tiles[a] > tiles[b]; });
         sc->h_work.reserve(work_n);
-        for (int i : order)
-            for (int t = 0; t < tiles[i]; ++t) sc->h_work.push_back(make_int2(i, t));
+        // frames of equal size go unit by unit, so the same unit of each (the
+        // same spectrum ranges, read again under another Doppler shift) runs
+        // at about the same time and its reads hit the caches
+        for (size_t g = 0; g < order.size();) {
+            size_t h = g;
+            while (h < order.size() && tiles[order[h]] == tiles[order[g]]) ++h;
+            for (int t = 0; t < tiles[order[g]]; ++t)
+                for (size_t q = g; q < h; ++q) sc->h_work.push_back(make_int2(order[q], t));
+            g = h;
+        }
     }
     if (noalloc) {
         // parameters travel as a kernel argument: no staging buffer
