@@ -112,19 +112,24 @@ def gpu_samples(frame_t, sc, rq, tw, th, seed=0, n_each=30, n_win=4):
 
 def measured_traffic():
     """HBM bytes per timed launch from the committed FETCH_SIZE / WRITE_SIZE
-    counter summary (copy-calibrated), or None when render_table's source has
-    changed since the counters were taken."""
+    counter summary (copy-calibrated), or None when render_table's source or
+    the host code that orders its work list has changed since the counters
+    were taken."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "render_table_c1_batch4_hbm_traffic.md")
-    src = os.path.join(ROOT, "paper_2008_05858_amd", "csrc", "k_table.hip")
+    csrc = os.path.join(ROOT, "paper_2008_05858_amd", "csrc")
+
+    def sha(name):
+        return hashlib.sha256(open(os.path.join(csrc, name), "rb").read()).hexdigest()
     try:
         txt = open(path).read()
         rec = json.loads(re.search(r"```json\n(.*?)\n```", txt, re.S).group(1))
-        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        same = (rec.get("kernel_source_sha256") == sha("k_table.hip") and
+                rec.get("host_source_sha256") == sha("api.cpp"))
     except (OSError, AttributeError, ValueError):
         return None
-    return rec["hbm_bytes_per_launch"] if rec.get("kernel_source_sha256") == cur else None
+    return rec["hbm_bytes_per_launch"] if same else None
 
 
 def cpu_info():
