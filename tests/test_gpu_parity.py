@@ -75,6 +75,20 @@ def test_mini_hires_frame():
     assert _report("mini_hires", g, o) < TOL
 
 
+@pytest.mark.parametrize("nx,out", [(509, "f64"), (510, "f32"), (508, "f64")])
+def test_table_frame_widths_and_fp64_out(nx, out):
+    """Table path on frames whose width is not a multiple of four pixels (the
+    tile write-out then stores pixel by pixel instead of four at a time) and
+    with FP64 output, against the oracle."""
+    sc = scene("mini_table", nx=nx, out_dtype=out)
+    rq = Request(rv_mps=2.0)
+    print(f"case mini_table nx={nx} out={out}", flush=True)
+    g = _gu().render(sc, rq)
+    o = oracle.render(sc, rq)
+    assert g.dtype == (np.float64 if out == "f64" else np.float32)
+    assert _report(f"mini_table nx={nx} {out}", g, o) < TOL
+
+
 def test_mini_sep_frame():
     sc = scene("mini_sep")
     print("case mini_sep FP64 accumulation", flush=True)
