@@ -15,8 +15,9 @@
 // One workgroup owns one detector tile (TW x 32 pixels) and writes each of
 // its pixels exactly once; no global atomics.  For every trace reaching the
 // tile (ascending trace order, then node cell) it
-//   1. gives each thread one slot column and finds that column's samples by
-//      a secant search on the FP64 format polynomial;
+//   1. gives each thread one slot column and finds that column's samples
+//      (an interpolated guess, secant steps, an exact test on the FP64
+//      format polynomial);
 //   2. walks those samples in order (spectrum values read four at a time,
 //      FP64 positions, FP64 moment sums per row run) into the column's
 //      private 4-row deposit window held in registers;
@@ -432,7 +433,9 @@ __global__ __launch_bounds__(kTableThreads, 3) void k_render_table(
                 // The sample index as a function of the slot coordinate,
                 // interpolated (Newton form) through the segment's first,
                 // middle and last samples: a guess within a small fraction of
-                // a sample, which the exact test below settles.
+                // a sample on moderately sampled segments (hundreds of samples
+                // off on densely sampled ones), which the secant steps and the
+                // exact test below settle.
                 const int km = k0 + ((k1 - 1 - k0) >> 1);
                 const double ua = u_of(k0), um = u_of(km), ub = u_of(k1 - 1);
                 double d1 = 0.0, d2 = 0.0;
