@@ -89,6 +89,40 @@ def test_table_frame_widths_and_fp64_out(nx, out):
     assert _report(f"mini_table nx={nx} {out}", g, o) < TOL
 
 
+@pytest.mark.parametrize("seed", [2001, 2011])
+def test_table_steep_traces(seed):
+    """Table path on traces close to the steepest the format loader accepts
+    (|dy/dx| up to 0.44 / 0.48, against 0.5): a column's samples change
+    deposit row every couple of columns, an item spans tens of bands, the
+    windows of neighbouring columns start on different rows, and a segment
+    can reach past the rows a tile carries into the next (it is then taken
+    up again there).  Against the oracle, with a Doppler shift."""
+    sc = scene("mini_table", seed=seed, b_total=70.0)
+    rq = Request(rv_mps=-4.0, flux_scale=1.7)
+    print(f"case mini_table steep seed={seed}", flush=True)
+    g = _gu().render(sc, rq)
+    o = oracle.render(sc, rq)
+    assert _report(f"mini_table steep {seed}", g, o) < TOL
+
+
+def test_table_trace_off_detector_edges():
+    """A table-path trace that starts left of the detector, leaves through the
+    right edge and grazes row 0 (120 x 40 px: three tile columns, the last
+    ragged, one tile row plus a ragged one; 2 x 2 field nodes), and the same
+    trace moved to graze the last row, against the oracle."""
+    from tests.test_oracle_gather import _off_edge_table_scene
+    sc = _off_edge_table_scene()
+    t = sc.traces[0]
+    top = dataclasses.replace(sc, name="off_edge_last_row",
+                              traces=[dataclasses.replace(t, cy=[37.6, 1.4, 0.8])])
+    rq = Request(rv_mps=3.0, flux_scale=2.0)
+    for s_ in (sc, top):
+        print(f"case {s_.name}", flush=True)
+        g = _gu().render(s_, rq)
+        o = oracle.render(s_, rq)
+        assert _report(s_.name, g, o) < TOL
+
+
 def test_mini_sep_frame():
     sc = scene("mini_sep")
     print("case mini_sep FP64 accumulation", flush=True)
