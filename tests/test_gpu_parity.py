@@ -263,3 +263,38 @@ def test_separable_precision_variants(prec):
     # the paper's photocentre budget (Sec. 1, Sec. 2.2): 1e-5 px
     assert np.isfinite(cg).all() and np.isfinite(co).all()
     assert abs(cg[0] - co[0]) <= 1e-5 and abs(cg[1] - co[1]) <= 1e-5
+
+
+def _steep_sep_scene():
+    """mini_sep's instrument with traces near the steepest accepted slope
+    (|dy/dx| up to 0.48)."""
+    from workloads.synth import _espresso
+    return _espresso(2011, nx=512, ny=452, orders=list(range(78, 82)), n_samp=20000, gx=11,
+                     kwid=0, psf_kind="separable", name="mini_sep_steep", xh=262.0, y0=60.0,
+                     pitch=100.0, n_lines=600, a_scale=0.06, b_total=70.0)
+
+
+def _off_edge_sep_scene():
+    """A separable-PSF trace entering and leaving through the side edges of a
+    120 x 40 px detector and grazing row 0, on a 2 x 2 field grid."""
+    rng = np.random.default_rng(12)
+    sig = rng.uniform(1.0, 1.6, (2, 2, 2)).astype(np.float32)
+    psf = Psf(kind="separable", gx=2, gy=2, half_width=8, sigma_xy=sig)
+    n = 3000
+    tr = Trace(0, 0, 0, 600.0, 603.0, n, [60.0, 70.0, 3.0, -1.5], [2.2, 1.4, 0.8], 0.7, 0)
+    spec = rng.uniform(0.5, 1.5, n) * 1e4
+    return Scene("off_edge_sep", 120, 40, [tr], psf, [spec.astype(np.float32)], "f32")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16_hilo", "bf16_hilo"])
+def test_separable_steep_and_off_edge(prec):
+    """The separable path (VALU at FP64 / FP32, MFMA at fp16 / bf16 hi-lo) on
+    steep traces, whose windows cross tile rows along the trace, and on a
+    trace running over the detector's edges, against the oracle, each
+    precision held to its bound."""
+    for sc in (_steep_sep_scene(), _off_edge_sep_scene()):
+        rq = Request(rv_mps=-3.0, flux_scale=1.3, precision=prec)
+        print(f"case {sc.name} precision={prec}", flush=True)
+        g = _gu().render(sc, rq)
+        o = oracle.render(sc, rq)
+        assert _report(f"{sc.name}-{prec}", g, o) < SEP_BOUNDS[prec]
