@@ -659,7 +659,7 @@ __global__ __launch_bounds__(kTableThreads, 3) void k_render_table(
                     double ry = py[0];
                     // the row changes (rare) unless 0 <= ry < 1: one unsigned
                     // compare of the high word (negative values have the sign bit)
-                    if ((unsigned)(__double_as_longlong(ry) >> 32) >= 0x3ff00000u) {
+                    if (__builtin_expect((unsigned)(__double_as_longlong(ry) >> 32) >= 0x3ff00000u, 0)) {
                         flush();
 #pragma unroll
                         for (int a = 0; a < 3; ++a)
