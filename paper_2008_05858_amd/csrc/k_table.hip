@@ -83,7 +83,7 @@ struct SpecVec<float> {
     static constexpr int G = 4;
     __device__ static void load(gptr<float> p, int k, int n, float v[4])
     {
-        if (k + 4 <= n) {
+        if (__builtin_expect(k + 4 <= n, 1)) {
             const f4u q = *(const __attribute__((address_space(1))) f4u *)(p + k);
             v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
         } else {
@@ -97,7 +97,7 @@ struct SpecVec<double> {
     static constexpr int G = 2;
     __device__ static void load(gptr<double> p, int k, int n, double v[2])
     {
-        if (k + 2 <= n) {
+        if (__builtin_expect(k + 2 <= n, 1)) {
             const d2u q = *(const __attribute__((address_space(1))) d2u *)(p + k);
             v[0] = q.x; v[1] = q.y;
         } else {
@@ -536,7 +536,7 @@ __global__ __launch_bounds__(kTableThreads, 3) void k_render_table(
 
                 auto flush = [&]() {
                     const int o = runQy - rb;
-                    if (o < 0 || o > 2) {
+                    if (__builtin_expect(o < 0 || o > 2, 0)) {
                         atomicOr(err, kErrRowWindow);
                         return;
                     }
@@ -582,7 +582,7 @@ __global__ __launch_bounds__(kTableThreads, 3) void k_render_table(
                     // rows runQy, runQy + 1 are window rows o, o + 1: fixed rows 1, 2
                     // for a column's first run (the usual case), selects otherwise
                     // (a dynamic index would move the window out of registers)
-                    if (o == 1) {
+                    if (__builtin_expect(o == 1, 1)) {
 #pragma unroll
                         for (int l = 0; l < 4; ++l)
 #pragma unroll
